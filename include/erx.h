@@ -1,0 +1,169 @@
+/*
+ * erx.h - C ABI of the MI355X (gfx950) ERX anomaly-detector library.
+ *
+ * ERX (exponentially moving RX) scores every pixel of each incoming scan line
+ * X_t in R^{p x b} (p pixels, b bands) by its Mahalanobis distance from a
+ * background whose mean and covariance are exponential moving averages over
+ * the lines seen so far:
+ *
+ *   mu_hat_t = (1/p) sum_i x_i,  K_hat_t = 1/(p-1) sum_i (x_i-mu_hat)(x_i-mu_hat)^T
+ *                                                    (paper Sec. III-C, Eqs. (18)-(19))
+ *   mu_t = (1-a) mu_{t-1} + a mu_hat_t,  K_t = (1-a) K_{t-1} + a K_hat_t
+ *       with the first line's statistics as the initial background
+ *                                                    (Sec. III-C, Eqs. (20)-(21))
+ *   L_t L_t^T = K_t + eps I,  L_t m_i = x_i - mu_t,  delta_i = sqrt(m_i . m_i)
+ *                                                    (Sec. III-D, Eqs. (22)-(23))
+ *   delta_N,i = (delta_i - mean(delta)) / std(delta) (Sec. III-E, Eq. (24))
+ *
+ * Each line is scored with the background after its own update.  The sparse
+ * random projection of Sec. III-B is not applied (every band is kept).
+ *
+ * Conventions for every entry point:
+ *   - Line buffers are row-major [n][pixels][bands], band index fastest.
+ *     They may be host or device pointers (detected with
+ *     hipPointerGetAttributes); host buffers may be reused as soon as the call
+ *     returns, device buffers must stay valid until the handle's stream has
+ *     executed the work (erx_synchronize, or any blocking call).
+ *   - The caller owns every buffer it passes; the library owns its handle,
+ *     the device-resident detector state and all scratch memory.
+ *   - Functions return ERX_OK (0) or a negative ERX_E* code and set a
+ *     thread-local message readable with erx_last_error().  Argument errors
+ *     (ERX_EINVAL) are detected before any work is enqueued, so the detector
+ *     state is unchanged.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef ERX_H
+#define ERX_H
+
+#include <stddef.h>
+
+#ifndef ERX_API
+#define ERX_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ERX_OK = 0,
+    ERX_EINVAL = -1,  /* invalid argument; nothing was enqueued */
+    ERX_ENOMEM = -2,  /* device or host allocation failed */
+    ERX_EDEVICE = -3, /* a HIP runtime call failed */
+    ERX_ENOTPD = -4,  /* returned by erx_scores* when at least one line of the last push had
+                         a regularised covariance that is not positive definite (possible only
+                         with ridge 0); those lines' scores are NaN, the others are valid */
+    ERX_ESTATE = -5   /* e.g. scores requested before any push */
+};
+
+/* storage type of the input lines */
+enum { ERX_F32 = 0, ERX_F16 = 1, ERX_U16 = 2 /* raw counts u, value u * 2^-16 */ };
+
+/* arithmetic of the per-line Gram (covariance) contraction */
+enum {
+    ERX_GRAM_FP32 = 0, /* FP32 matrix cores, FP32 partials per <=64-pixel chunk, FP64 sums */
+    ERX_GRAM_BF16 = 1, /* BF16 inputs on the matrix cores, FP32 accumulate */
+    ERX_GRAM_FP16 = 2  /* FP16 inputs on the matrix cores, FP32 accumulate */
+};
+
+typedef struct erx_ctx erx_ctx;
+
+typedef struct erx_config {
+    int bands;       /* b >= 1 (at most ERX_MAX_BANDS) */
+    int pixels;      /* p >= 2 (the line covariance divides by p-1) */
+    float momentum;  /* a in (0, 1]; the paper's default is 0.1 */
+    float ridge;     /* eps >= 0 added to the covariance diagonal; default 1e-5 */
+    int warmup;      /* lines flagged as warm-up buffer (paper: 99); scores are still computed,
+                        only the labels of erx_labels are forced to 0 for them */
+    int dtype;       /* ERX_F32 / ERX_F16 / ERX_U16 */
+    int precision;   /* ERX_GRAM_* */
+    double fp64_cond_threshold; /* 0 (default): every line is factored in FP64.  > 0: lines are
+                                   factored in FP32 and those whose 1-norm condition estimate of
+                                   K_t + eps I exceeds this (or that meet a non-positive pivot) are
+                                   re-factored in FP64; +inf: FP32 only */
+    int normalise;   /* 1: also produce line-normalised scores (erx_scores_normalised) */
+    int block_lines; /* lines per device pass (scratch is sized for it); default 2048 */
+    int scan_lines;  /* lines per segment of the chunked moving-average scan; default 64 */
+} erx_config;
+
+#define ERX_MAX_BANDS 304
+
+/* Fill *cfg with defaults: ridge 1e-5, warmup 0, F32 input, FP32 Gram,
+ * threshold 0 (FP64 factorisation), no normalisation, block_lines 2048,
+ * scan_lines 64. */
+ERX_API void erx_config_default(erx_config *cfg, int bands, int pixels, float momentum);
+
+/* Create a detector on the current HIP device.  Returns NULL on error
+ * (erx_last_error says why).  erx_create uses the defaults above. */
+ERX_API erx_ctx *erx_create(int bands, int pixels, float momentum);
+ERX_API erx_ctx *erx_create_ex(const erx_config *cfg);
+
+/* Run the handle's later work on a caller-provided hipStream_t (NULL is the
+ * device's default stream).  Until this is called the handle uses a stream of
+ * its own.  The stream must outlive its use by the handle. */
+ERX_API int erx_set_stream(erx_ctx *h, void *hip_stream);
+
+/* Absorb and score n >= 1 lines (Sec. III, one line at a time, in order).
+ * erx_push_lines takes FP32 lines; erx_push_lines_ex takes the configured
+ * dtype.  Stream-ordered: returns once the work is enqueued (host input is
+ * staged before return). */
+ERX_API int erx_push_lines(erx_ctx *h, const float *lines, int n);
+ERX_API int erx_push_lines_ex(erx_ctx *h, const void *lines, int n);
+
+/* Scores of the last push, [n][pixels] FP32 distances delta.  erx_scores
+ * copies to host memory and blocks; erx_scores_device copies into a device
+ * buffer on the handle's stream without blocking. */
+ERX_API int erx_scores(erx_ctx *h, float *out);
+ERX_API int erx_scores_device(erx_ctx *h, float *dev_out);
+
+/* Line-normalised scores of the last push (needs cfg.normalise = 1). */
+ERX_API int erx_scores_normalised(erx_ctx *h, float *out);
+
+/* Labels y = [delta_N >= tau] of the last push as bytes [n][pixels] (Sec. III-E,
+ * Eq. (25)); warm-up lines give 0.  Needs cfg.normalise = 1.  Host output. */
+ERX_API int erx_labels(erx_ctx *h, float tau, unsigned char *out);
+
+/* Detector state: number of lines absorbed, background mean [b] and full
+ * symmetric covariance [b*b] (FP64, host buffers).  erx_set_state with t = 0
+ * resets the detector; the next line initialises the background. */
+ERX_API int erx_get_state(erx_ctx *h, long long *t, double *mu, double *K);
+ERX_API int erx_set_state(erx_ctx *h, long long t, const double *mu, const double *K);
+
+typedef struct erx_stats_t {
+    long long lines;          /* lines absorbed */
+    long long fp64_refactors; /* lines re-factored in FP64 */
+    long long notpd;          /* lines whose covariance was not positive definite */
+    double max_cond;          /* largest 1-norm condition estimate seen */
+} erx_stats_t;
+ERX_API int erx_stats(erx_ctx *h, erx_stats_t *out);
+
+/* Per-line diagnostics of the last push (host buffers of n entries, either may
+ * be NULL): condition estimate and status bits (1 = FP64 re-factor requested,
+ * 2 = re-factored in FP64, 4 = not positive definite). */
+ERX_API int erx_line_info(erx_ctx *h, float *cond, int *flags);
+
+/* Kernel timing: when enabled, every kernel launch of the handle is bracketed
+ * by HIP events on the handle's stream.  erx_profile_read waits for the
+ * stream, writes up to max entries (kernel name, launches, total
+ * milliseconds) in a fixed kernel order, returns the number of entries and
+ * clears the record. */
+typedef struct erx_kernel_time {
+    char name[32];
+    long long launches;
+    double total_ms;
+} erx_kernel_time;
+ERX_API int erx_profile_enable(erx_ctx *h, int on);
+ERX_API int erx_profile_read(erx_ctx *h, erx_kernel_time *out, int max);
+
+/* Wait for all work enqueued on the handle's stream. */
+ERX_API int erx_synchronize(erx_ctx *h);
+
+ERX_API void erx_destroy(erx_ctx *h);
+
+/* Thread-local description of the last error (never NULL). */
+ERX_API const char *erx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ERX_H */

@@ -1,0 +1,267 @@
+"""Python binding of the ERX gfx950 library (include/erx.h).
+
+Argument marshalling only: every step of the detector runs in the HIP kernels
+of liberx.so.  PyTorch is used for device memory and streams.  There is no
+fallback: if the library is missing or cannot be loaded, every entry point
+raises ErxError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liberx.so")
+
+ERX_OK, ERX_EINVAL, ERX_ENOMEM, ERX_EDEVICE, ERX_ENOTPD, ERX_ESTATE = 0, -1, -2, -3, -4, -5
+DTYPES = {"f32": 0, "f16": 1, "u16": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+FLAG_NEED_FP64, FLAG_FP64_DONE, FLAG_NOTPD = 1, 2, 4
+MAX_BANDS = 304
+
+# every entry point declared in include/erx.h
+EXPORTS = (
+    "erx_config_default", "erx_create", "erx_create_ex", "erx_set_stream", "erx_push_lines",
+    "erx_push_lines_ex", "erx_scores", "erx_scores_device", "erx_scores_normalised", "erx_labels",
+    "erx_get_state", "erx_set_state", "erx_stats", "erx_line_info", "erx_profile_enable",
+    "erx_profile_read", "erx_synchronize", "erx_destroy", "erx_last_error",
+)
+
+
+class ErxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("bands", C.c_int), ("pixels", C.c_int), ("momentum", C.c_float),
+                ("ridge", C.c_float), ("warmup", C.c_int), ("dtype", C.c_int),
+                ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
+                ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int)]
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_longlong), ("total_ms", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("lines", C.c_longlong), ("fp64_refactors", C.c_longlong),
+                ("notpd", C.c_longlong), ("max_cond", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liberx.so and declare its signatures (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ErxError(ERX_EDEVICE, f"{path} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, ip = C.c_void_p, C.c_int
+    sig = {
+        "erx_config_default": (None, [C.POINTER(Config), ip, ip, C.c_float]),
+        "erx_create": (vp, [ip, ip, C.c_float]),
+        "erx_create_ex": (vp, [C.POINTER(Config)]),
+        "erx_set_stream": (ip, [vp, vp]),
+        "erx_push_lines": (ip, [vp, vp, ip]),
+        "erx_push_lines_ex": (ip, [vp, vp, ip]),
+        "erx_scores": (ip, [vp, vp]),
+        "erx_scores_device": (ip, [vp, vp]),
+        "erx_scores_normalised": (ip, [vp, vp]),
+        "erx_labels": (ip, [vp, C.c_float, vp]),
+        "erx_get_state": (ip, [vp, C.POINTER(C.c_longlong), vp, vp]),
+        "erx_set_state": (ip, [vp, C.c_longlong, vp, vp]),
+        "erx_stats": (ip, [vp, C.POINTER(Stats)]),
+        "erx_line_info": (ip, [vp, vp, vp]),
+        "erx_profile_enable": (ip, [vp, ip]),
+        "erx_profile_read": (ip, [vp, C.POINTER(KernelTime), ip]),
+        "erx_synchronize": (ip, [vp]),
+        "erx_destroy": (None, [vp]),
+        "erx_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().erx_last_error().decode()
+
+
+def _check(rc: int, allow=()):
+    if rc != ERX_OK and rc not in allow:
+        raise ErxError(rc, last_error())
+    return rc
+
+
+def _ptr(x) -> int:
+    """Data pointer of a contiguous torch tensor or numpy array."""
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Detector:
+    """One ERX stream on the current GPU (a handle of the C library)."""
+
+    def __init__(self, bands: int, pixels: int, momentum: float = 0.1, ridge: float = 1e-5,
+                 dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
+                 normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
+                 scan_lines: int = 64, stream: Optional[int] = -1):
+        """stream: hipStream_t handle to run on; -1 (default) = torch's current
+        stream, None = a stream owned by the handle."""
+        lib = load()
+        cfg = Config()
+        lib.erx_config_default(C.byref(cfg), int(bands), int(pixels), float(momentum))
+        cfg.ridge = float(ridge)
+        cfg.dtype = DTYPES[dtype]
+        cfg.precision = PRECISIONS[precision]
+        cfg.fp64_cond_threshold = float(fp64_cond_threshold)
+        cfg.normalise = 1 if normalise else 0
+        cfg.warmup = int(warmup)
+        cfg.block_lines = int(block_lines)
+        cfg.scan_lines = int(scan_lines)
+        self.cfg = cfg
+        self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
+        self._lib = lib
+        self._h = lib.erx_create_ex(C.byref(cfg))
+        if not self._h:
+            raise ErxError(ERX_EINVAL, last_error())
+        self.last_n = 0
+        if stream == -1:
+            stream = _torch_stream()
+        if stream is not None:
+            _check(lib.erx_set_stream(self._h, C.c_void_p(stream)))
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.erx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- work
+    def push(self, lines) -> "Detector":
+        """Absorb and score lines [n, pixels, bands] (torch tensor or numpy array)."""
+        shape = tuple(lines.shape)
+        if len(shape) == 2:
+            shape = (1,) + shape
+        if shape[1:] != (self.pixels, self.bands):
+            raise ValueError(f"lines must be [n, {self.pixels}, {self.bands}], got {tuple(lines.shape)}")
+        _check(self._lib.erx_push_lines_ex(self._h, C.c_void_p(_ptr(lines)), int(shape[0])))
+        self.last_n = int(shape[0])
+        return self
+
+    def scores(self, out=None, allow_notpd: bool = True):
+        """Scores of the last push as a [n, pixels] float32 torch tensor on the GPU."""
+        import torch
+        if out is None:
+            out = torch.empty((self.last_n, self.pixels), dtype=torch.float32, device="cuda")
+        _check(self._lib.erx_scores_device(self._h, C.c_void_p(_ptr(out))))
+        return out
+
+    def scores_host(self, allow_notpd: bool = True) -> np.ndarray:
+        out = np.empty((self.last_n, self.pixels), np.float32)
+        _check(self._lib.erx_scores(self._h, C.c_void_p(out.ctypes.data)),
+               allow=(ERX_ENOTPD,) if allow_notpd else ())
+        return out
+
+    def scores_normalised(self, allow_notpd: bool = True) -> np.ndarray:
+        out = np.empty((self.last_n, self.pixels), np.float32)
+        _check(self._lib.erx_scores_normalised(self._h, C.c_void_p(out.ctypes.data)),
+               allow=(ERX_ENOTPD,) if allow_notpd else ())
+        return out
+
+    def labels(self, tau: float) -> np.ndarray:
+        out = np.empty((self.last_n, self.pixels), np.uint8)
+        _check(self._lib.erx_labels(self._h, C.c_float(tau), C.c_void_p(out.ctypes.data)))
+        return out
+
+    def synchronize(self):
+        _check(self._lib.erx_synchronize(self._h))
+
+    # -- state and diagnostics
+    def state(self):
+        t = C.c_longlong(0)
+        mu = np.empty(self.bands)
+        K = np.empty((self.bands, self.bands))
+        _check(self._lib.erx_get_state(self._h, C.byref(t), C.c_void_p(mu.ctypes.data),
+                                       C.c_void_p(K.ctypes.data)))
+        return int(t.value), mu, K
+
+    def set_state(self, t: int, mu=None, K=None):
+        mu = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64)
+        K = None if K is None else np.ascontiguousarray(K, dtype=np.float64)
+        _check(self._lib.erx_set_state(self._h, int(t),
+                                       None if mu is None else C.c_void_p(mu.ctypes.data),
+                                       None if K is None else C.c_void_p(K.ctypes.data)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.erx_stats(self._h, C.byref(s)))
+        return dict(lines=s.lines, fp64_refactors=s.fp64_refactors, notpd=s.notpd,
+                    max_cond=s.max_cond)
+
+    def profile(self, on: bool = True):
+        """Bracket every kernel launch with HIP events on the handle's stream."""
+        _check(self._lib.erx_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel: (launches, total_ms)} since the last read (waits for the stream)."""
+        buf = (KernelTime * 16)()
+        k = self._lib.erx_profile_read(self._h, buf, 16)
+        if k < 0:
+            raise ErxError(k, last_error())
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(k)}
+
+    def line_info(self):
+        cond = np.empty(self.last_n, np.float32)
+        flags = np.empty(self.last_n, np.int32)
+        _check(self._lib.erx_line_info(self._h, C.c_void_p(cond.ctypes.data),
+                                       C.c_void_p(flags.ctypes.data)))
+        return cond, flags
+
+
+__all__ = ["Detector", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
+           "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "MAX_BANDS"]

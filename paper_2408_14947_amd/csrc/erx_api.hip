@@ -1,0 +1,526 @@
+// C-ABI runtime of the ERX library: handles, validation, device memory, the
+// per-pass launch sequence and the state / diagnostics accessors.  All
+// arithmetic of the detector runs in the kernels of erx_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/erx.h"
+#include "erx_internal.h"
+
+using namespace erx;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(ERX_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_size(int dtype) { return dtype == ERX_F32 ? 4 : 2; }
+
+}  // namespace
+
+struct erx_ctx {
+    erx_config cfg;
+    int NT = 0, NTL = 0, bpad = 0;
+    long long E = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    long long t = 0;  // lines absorbed
+    // device memory
+    double* state = nullptr;   // [E] background after line t (packed, FP64)
+    double* stats = nullptr;   // [C][E] per-line statistics, then segment-local scan
+    double* carry = nullptr;   // [nseg][E] background entering each scan segment
+    float* Mt = nullptr;       // [C][NTL][256] inverse-factor tiles
+    float* mu32 = nullptr;     // [C][bpad] background mean per line
+    unsigned long long* ctr = nullptr;  // fp64 re-factors, not-PD lines, max cond (float bits)
+    int* flags = nullptr;      // [cap] per line of the last push
+    float* cond = nullptr;     // [cap]
+    float* scores = nullptr;   // [cap][p]
+    float* scores_n = nullptr; // [cap][p]
+    unsigned char* labels = nullptr;  // [cap][p]
+    void* staging = nullptr;   // [C][p][b] host-input staging
+    long long cap = 0;
+    int last_n = 0;
+    long long last_t0 = 0;
+    bool have_scores = false;
+    // kernel timing
+    bool profile = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Rec { int kernel; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+};
+
+namespace {
+
+enum { K_GRAM, K_SCAN_LOCAL, K_SCAN_CARRY, K_CHOL32, K_CHOL64, K_SCORE, K_NORMALISE, K_COUNT };
+const char* kKernelNames[K_COUNT] = {"gram", "scan_local", "scan_carry", "chol_fp32", "chol_fp64",
+                                     "score", "normalise"};
+
+hipEvent_t take_event(erx_ctx* h)
+{
+    if (h->ev_pool.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+}
+
+// run one launch, bracketed by events when profiling is on
+template <class F> hipError_t timed(erx_ctx* h, int kernel, F&& launch)
+{
+    if (!h->profile) return launch();
+    hipEvent_t a = take_event(h), b = take_event(h);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, h->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+    h->recs.push_back({kernel, a, b});
+    return e;
+}
+
+}  // namespace
+
+namespace {
+
+void free_all(erx_ctx* h)
+{
+    void* ptrs[] = {h->state, h->stats, h->carry, h->Mt, h->mu32, h->ctr, h->flags, h->cond,
+                    h->scores, h->scores_n, h->labels, h->staging};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& r : h->recs) {
+        h->ev_pool.push_back(r.a);
+        h->ev_pool.push_back(r.b);
+    }
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+}
+
+template <class T> hipError_t dmalloc(T** p, size_t bytes)
+{
+    return hipMalloc((void**)p, bytes ? bytes : 16);
+}
+
+int ensure_capacity(erx_ctx* h, long long n)
+{
+    if (n <= h->cap) return ERX_OK;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    void* old[] = {h->flags, h->cond, h->scores, h->scores_n, h->labels};
+    for (void* p : old)
+        if (p) (void)hipFree(p);
+    h->flags = nullptr;
+    h->cond = nullptr;
+    h->scores = h->scores_n = nullptr;
+    h->labels = nullptr;
+    h->cap = 0;
+    const size_t p = (size_t)h->cfg.pixels;
+    if (dmalloc(&h->flags, n * sizeof(int)) != hipSuccess || dmalloc(&h->cond, n * sizeof(float)) != hipSuccess ||
+        dmalloc(&h->scores, n * p * sizeof(float)) != hipSuccess ||
+        (h->cfg.normalise && dmalloc(&h->scores_n, n * p * sizeof(float)) != hipSuccess) ||
+        (h->cfg.normalise && dmalloc(&h->labels, n * p) != hipSuccess)) {
+        (void)hipGetLastError();
+        return fail(ERX_ENOMEM, "cannot allocate result buffers for %lld lines", n);
+    }
+    h->cap = n;
+    return ERX_OK;
+}
+
+bool is_device_ptr(const void* ptr)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// offset of element (r, c) of the packed upper triangle (r <= c in tile terms)
+long long packed_offset(int r, int c, int NT)
+{
+    const int I = r >> 4, J = c >> 4, rr = r & 15, cc = c & 15;
+    const long long u = (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
+    return u * 256 + (16 * (rr >> 2) + cc) * 4 + (rr & 3);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* erx_last_error(void) { return g_err.c_str(); }
+
+void erx_config_default(erx_config* cfg, int bands, int pixels, float momentum)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->bands = bands;
+    cfg->pixels = pixels;
+    cfg->momentum = momentum;
+    cfg->ridge = 1e-5f;
+    cfg->warmup = 0;
+    cfg->dtype = ERX_F32;
+    cfg->precision = ERX_GRAM_FP32;
+    cfg->fp64_cond_threshold = 0.0;
+    cfg->normalise = 0;
+    cfg->block_lines = 2048;
+    cfg->scan_lines = 64;
+}
+
+erx_ctx* erx_create_ex(const erx_config* cfg)
+{
+    if (!cfg) {
+        fail(ERX_EINVAL, "erx_create_ex: cfg is NULL");
+        return nullptr;
+    }
+    const erx_config& c = *cfg;
+    if (c.bands < 1 || c.bands > ERX_MAX_BANDS) {
+        fail(ERX_EINVAL, "bands must be in [1, %d], got %d", ERX_MAX_BANDS, c.bands);
+        return nullptr;
+    }
+    if (c.pixels < 2) {
+        fail(ERX_EINVAL, "pixels must be >= 2 (the line covariance divides by p-1), got %d", c.pixels);
+        return nullptr;
+    }
+    if (!(c.momentum > 0.0f && c.momentum <= 1.0f)) {
+        fail(ERX_EINVAL, "momentum must be in (0, 1], got %g", (double)c.momentum);
+        return nullptr;
+    }
+    if (!(c.ridge >= 0.0f) || !std::isfinite(c.ridge)) {
+        fail(ERX_EINVAL, "ridge must be finite and >= 0, got %g", (double)c.ridge);
+        return nullptr;
+    }
+    if (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16) {
+        fail(ERX_EINVAL, "unknown dtype %d", c.dtype);
+        return nullptr;
+    }
+    if (c.precision != ERX_GRAM_FP32) {
+        fail(ERX_EINVAL, "precision %d is not available", c.precision);
+        return nullptr;
+    }
+    if (!(c.fp64_cond_threshold >= 0.0)) {
+        fail(ERX_EINVAL, "fp64_cond_threshold must be >= 0");
+        return nullptr;
+    }
+    if (c.block_lines < 1 || c.scan_lines < 1 || c.warmup < 0 || (c.normalise != 0 && c.normalise != 1)) {
+        fail(ERX_EINVAL, "block_lines and scan_lines must be >= 1, warmup >= 0, normalise 0/1");
+        return nullptr;
+    }
+    erx_ctx* h = new (std::nothrow) erx_ctx();
+    if (!h) {
+        fail(ERX_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    h->cfg = c;
+    h->NT = (c.bands + 15) / 16;
+    h->NTL = h->NT * (h->NT + 1) / 2;
+    h->bpad = 16 * h->NT;
+    h->E = stat_entries(h->NT);
+    const size_t C = (size_t)c.block_lines;
+    const size_t nseg = (C + c.scan_lines - 1) / c.scan_lines;
+    bool ok = hipGetDevice(&h->device) == hipSuccess && hipStreamCreate(&h->own_stream) == hipSuccess;
+    h->stream = h->own_stream;
+    ok = ok && dmalloc(&h->state, h->E * sizeof(double)) == hipSuccess &&
+         dmalloc(&h->stats, C * h->E * sizeof(double)) == hipSuccess &&
+         dmalloc(&h->carry, nseg * h->E * sizeof(double)) == hipSuccess &&
+         dmalloc(&h->Mt, C * h->NTL * 256 * sizeof(float)) == hipSuccess &&
+         dmalloc(&h->mu32, C * h->bpad * sizeof(float)) == hipSuccess &&
+         dmalloc(&h->ctr, 4 * sizeof(unsigned long long)) == hipSuccess;
+    ok = ok && hipMemset(h->state, 0, h->E * sizeof(double)) == hipSuccess &&
+         hipMemset(h->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
+    if (!ok) {
+        const hipError_t e = hipGetLastError();
+        free_all(h);
+        delete h;
+        fail(ERX_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    return h;
+}
+
+erx_ctx* erx_create(int bands, int pixels, float momentum)
+{
+    erx_config c;
+    erx_config_default(&c, bands, pixels, momentum);
+    return erx_create_ex(&c);
+}
+
+int erx_set_stream(erx_ctx* h, void* s)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->stream = (hipStream_t)s;
+    return ERX_OK;
+}
+
+int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    if (!lines || n < 1) return fail(ERX_EINVAL, "need a non-NULL line buffer and n >= 1 (got n=%d)", n);
+    const erx_config& c = h->cfg;
+    int rc = ensure_capacity(h, n);
+    if (rc) return rc;
+    const bool dev = is_device_ptr(lines);
+    const size_t esz = elem_size(c.dtype);
+    if (dev && ((uintptr_t)lines % (4 * esz)) != 0)
+        return fail(ERX_EINVAL, "device line buffer must be aligned to 4 elements (%zu bytes)", 4 * esz);
+    const size_t line_bytes = (size_t)c.pixels * c.bands * esz;
+    const int C = c.block_lines, seg = c.scan_lines;
+    if (!dev && !h->staging) {
+        if (hipMalloc(&h->staging, (size_t)C * line_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ERX_ENOMEM, "cannot allocate the input staging buffer");
+        }
+    }
+    const double thr = c.fp64_cond_threshold;
+    const int want_cond = std::isinf(thr) ? 0 : 1;
+    const bool fp64_pass = !std::isinf(thr);
+    h->last_t0 = h->t;
+    for (int c0 = 0; c0 < n; c0 += C) {
+        const int nc = (n - c0) < C ? (n - c0) : C;
+        const void* src;
+        if (dev) {
+            src = (const char*)lines + (size_t)c0 * line_bytes;
+        } else {
+            HIPCHK(hipMemcpyAsync(h->staging, (const char*)lines + (size_t)c0 * line_bytes, nc * line_bytes,
+                                  hipMemcpyHostToDevice, h->stream));
+            src = h->staging;
+        }
+        const long long t0 = h->t;
+        HIPCHK(timed(h, K_GRAM, [&] { return launch_gram(c.dtype, src, nc, c.pixels, c.bands, h->NT, h->stats,
+                                                          h->E, h->stream); }));
+        HIPCHK(timed(h, K_SCAN_LOCAL, [&] { return launch_scan_local(h->stats, h->E, nc, seg, t0, c.momentum,
+                                                                      h->stream); }));
+        HIPCHK(timed(h, K_SCAN_CARRY, [&] { return launch_scan_carry(h->stats, h->carry, h->state, h->E, nc,
+                                                                      seg, t0, c.momentum, h->stream); }));
+        if (thr > 0.0) {
+            // FP32 factorisation; lines whose condition estimate exceeds thr are re-factored in FP64
+            HIPCHK(timed(h, K_CHOL32, [&] {
+                return launch_chol(0, 0, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
+                                   c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, want_cond, h->ctr,
+                                   h->stream);
+            }));
+            if (fp64_pass)
+                HIPCHK(timed(h, K_CHOL64, [&] {
+                    return launch_chol(1, 0, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
+                                       c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, 1, h->ctr,
+                                       h->stream);
+                }));
+        } else {
+            // every line factored in FP64
+            HIPCHK(timed(h, K_CHOL64, [&] {
+                return launch_chol(1, 1, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
+                                   c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, 1, h->ctr,
+                                   h->stream);
+            }));
+        }
+        float* out = h->scores + (size_t)c0 * c.pixels;
+        HIPCHK(timed(h, K_SCORE, [&] { return launch_score(c.dtype, h->NT, src, h->Mt, h->mu32, nc, c.pixels,
+                                                            c.bands, out, h->stream); }));
+        if (c.normalise)
+            HIPCHK(timed(h, K_NORMALISE, [&] { return launch_normalise(out, h->scores_n + (size_t)c0 * c.pixels,
+                                                                        nc, c.pixels, h->stream); }));
+        h->t += nc;
+        if (!dev) HIPCHK(hipStreamSynchronize(h->stream));  // the staging buffer is reused
+    }
+    h->last_n = n;
+    h->have_scores = true;
+    return ERX_OK;
+}
+
+int erx_push_lines(erx_ctx* h, const float* lines, int n)
+{
+    if (h && h->cfg.dtype != ERX_F32) return fail(ERX_EINVAL, "erx_push_lines needs a F32 handle");
+    return erx_push_lines_ex(h, lines, n);
+}
+
+static int check_notpd(erx_ctx* h)
+{
+    std::vector<int> f(h->last_n);
+    HIPCHK(hipMemcpyAsync(f.data(), h->flags, f.size() * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int v : f)
+        if (v & FLAG_NOTPD) return fail(ERX_ENOTPD, "at least one line had a covariance that is not positive definite");
+    return ERX_OK;
+}
+
+int erx_scores(erx_ctx* h, float* out)
+{
+    if (!h || !out) return fail(ERX_EINVAL, "NULL argument");
+    if (!h->have_scores) return fail(ERX_ESTATE, "no lines pushed yet");
+    const size_t bytes = (size_t)h->last_n * h->cfg.pixels * sizeof(float);
+    HIPCHK(hipMemcpyAsync(out, h->scores, bytes, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return check_notpd(h);
+}
+
+int erx_scores_device(erx_ctx* h, float* dev_out)
+{
+    if (!h || !dev_out) return fail(ERX_EINVAL, "NULL argument");
+    if (!h->have_scores) return fail(ERX_ESTATE, "no lines pushed yet");
+    const size_t bytes = (size_t)h->last_n * h->cfg.pixels * sizeof(float);
+    HIPCHK(hipMemcpyAsync(dev_out, h->scores, bytes, hipMemcpyDeviceToDevice, h->stream));
+    return ERX_OK;
+}
+
+int erx_scores_normalised(erx_ctx* h, float* out)
+{
+    if (!h || !out) return fail(ERX_EINVAL, "NULL argument");
+    if (!h->cfg.normalise) return fail(ERX_EINVAL, "handle created without normalise = 1");
+    if (!h->have_scores) return fail(ERX_ESTATE, "no lines pushed yet");
+    const size_t bytes = (size_t)h->last_n * h->cfg.pixels * sizeof(float);
+    HIPCHK(hipMemcpyAsync(out, h->scores_n, bytes, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return check_notpd(h);
+}
+
+int erx_labels(erx_ctx* h, float tau, unsigned char* out)
+{
+    if (!h || !out) return fail(ERX_EINVAL, "NULL argument");
+    if (!h->cfg.normalise) return fail(ERX_EINVAL, "handle created without normalise = 1");
+    if (!h->have_scores) return fail(ERX_ESTATE, "no lines pushed yet");
+    HIPCHK(launch_labels(h->scores_n, h->last_n, h->cfg.pixels, tau, h->last_t0, h->cfg.warmup, h->labels,
+                         h->stream));
+    HIPCHK(hipMemcpyAsync(out, h->labels, (size_t)h->last_n * h->cfg.pixels, hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ERX_OK;
+}
+
+int erx_get_state(erx_ctx* h, long long* t, double* mu, double* K)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    std::vector<double> s(h->E);
+    HIPCHK(hipMemcpyAsync(s.data(), h->state, h->E * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int b = h->cfg.bands, NT = h->NT;
+    if (t) *t = h->t;
+    if (mu)
+        for (int j = 0; j < b; ++j) mu[j] = s[(size_t)h->NTL * 256 + j];
+    if (K)
+        for (int r = 0; r < b; ++r)
+            for (int c = 0; c < b; ++c)
+                K[(size_t)r * b + c] = (r <= c) ? s[packed_offset(r, c, NT)] : s[packed_offset(c, r, NT)];
+    return ERX_OK;
+}
+
+int erx_set_state(erx_ctx* h, long long t, const double* mu, const double* K)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    if (t < 0) return fail(ERX_EINVAL, "t must be >= 0");
+    if (t > 0 && (!mu || !K)) return fail(ERX_EINVAL, "mu and K are required when t > 0");
+    std::vector<double> s(h->E, 0.0);
+    const int b = h->cfg.bands, NT = h->NT;
+    if (t > 0) {
+        for (int j = 0; j < b; ++j) s[(size_t)h->NTL * 256 + j] = mu[j];
+        for (int r = 0; r < b; ++r)
+            for (int c = r; c < b; ++c) s[packed_offset(r, c, NT)] = K[(size_t)r * b + c];
+    }
+    HIPCHK(hipMemcpyAsync(h->state, s.data(), h->E * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->t = t;
+    h->have_scores = false;
+    return ERX_OK;
+}
+
+int erx_stats(erx_ctx* h, erx_stats_t* out)
+{
+    if (!h || !out) return fail(ERX_EINVAL, "NULL argument");
+    unsigned long long c[4];
+    HIPCHK(hipMemcpyAsync(c, h->ctr, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    out->lines = h->t;
+    out->fp64_refactors = (long long)c[0];
+    out->notpd = (long long)c[1];
+    float mc;
+    const unsigned int bits = (unsigned int)(c[2] & 0xffffffffull);
+    std::memcpy(&mc, &bits, sizeof mc);
+    out->max_cond = mc;
+    return ERX_OK;
+}
+
+int erx_line_info(erx_ctx* h, float* cond, int* flags)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    if (!h->have_scores) return fail(ERX_ESTATE, "no lines pushed yet");
+    if (cond)
+        HIPCHK(hipMemcpyAsync(cond, h->cond, (size_t)h->last_n * sizeof(float), hipMemcpyDefault, h->stream));
+    if (flags)
+        HIPCHK(hipMemcpyAsync(flags, h->flags, (size_t)h->last_n * sizeof(int), hipMemcpyDefault, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ERX_OK;
+}
+
+int erx_profile_enable(erx_ctx* h, int on)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    h->profile = on != 0;
+    return ERX_OK;
+}
+
+int erx_profile_read(erx_ctx* h, erx_kernel_time* out, int max)
+{
+    if (!h || (max > 0 && !out) || max < 0) return fail(ERX_EINVAL, "bad arguments");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double ms[K_COUNT] = {0};
+    long long cnt[K_COUNT] = {0};
+    for (auto& r : h->recs) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.kernel] += t;
+        cnt[r.kernel] += 1;
+        h->ev_pool.push_back(r.a);
+        h->ev_pool.push_back(r.b);
+    }
+    h->recs.clear();
+    int k = 0;
+    for (int i = 0; i < K_COUNT && k < max; ++i) {
+        if (!cnt[i]) continue;
+        std::snprintf(out[k].name, sizeof out[k].name, "%s", kKernelNames[i]);
+        out[k].launches = cnt[i];
+        out[k].total_ms = ms[i];
+        ++k;
+    }
+    return k;
+}
+
+int erx_synchronize(erx_ctx* h)
+{
+    if (!h) return fail(ERX_EINVAL, "NULL handle");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return ERX_OK;
+}
+
+void erx_destroy(erx_ctx* h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,1002 @@
+// HIP kernels of the ERX hot path for gfx950 (CDNA4).
+//
+// One pass over a block of n consecutive lines of one stream runs:
+//   k_gram        per-line mean and centred Gram on FP32 matrix cores
+//                 (paper Sec. III-C, Eqs. (18)-(19))
+//   k_scan_local  segment-local exponential moving average (Eqs. (20)-(21))
+//   k_scan_carry  carries between segments (and into the next pass)
+//   k_chol        ridge + Cholesky + triangular inverse + condition estimate
+//                 (Sec. III-D), FP32 with an FP64 re-factor of flagged lines
+//   k_score       residual, whitening product L^{-1}(x - mu), row norm
+//                 (Sec. III-D, Eqs. (22)-(23)) on FP32 matrix cores
+//   k_normalise   line-wise standardisation (Sec. III-E, Eq. (24))
+//
+// Matrix tiles are 16x16 and are kept in the accumulator layout of the
+// 16x16x4 MFMA instructions: lane l = 16*g + c holds four rows of column c
+// (FP32: register i <-> row 4g+i; FP64: register i <-> row 4i+g).  With that
+// layout four MFMAs whose A and B operands are register i of two such tiles
+// X and Y compute X^T Y (in the same layout), so tiles produced by one
+// product feed the next without any data movement.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <type_traits>
+
+#include "erx_internal.h"
+
+namespace erx {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <class T> struct VT;
+template <> struct VT<float> { typedef f4 v; };
+template <> struct VT<double> { typedef d4 v; };
+
+// Row held by lane (g, c), register i, of a 16x16 accumulator tile.  The
+// 16x16x4 FP32 MFMA places row 4g+i there, the FP64 one row 4i+g.  Products
+// X^T Y are layout-agnostic (the contraction runs over every row once), so
+// only code that names rows explicitly uses this.
+template <class T> __device__ __forceinline__ int rowof(int g, int i)
+{
+    return std::is_same<T, double>::value ? 4 * i + g : 4 * g + i;
+}
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// acc += X^T Y for two accumulator-layout tiles held as register quadruples
+template <class V>
+__device__ __forceinline__ V mma_xty(V acc, const V x, const V y)
+{
+    acc = mfma(x[0], y[0], acc);
+    acc = mfma(x[1], y[1], acc);
+    acc = mfma(x[2], y[2], acc);
+    acc = mfma(x[3], y[3], acc);
+    return acc;
+}
+
+// ---------------------------------------------------------------- input loads
+template <int DT> __device__ __forceinline__ float ld1(const void* X, size_t i);
+template <> __device__ __forceinline__ float ld1<DT_F32>(const void* X, size_t i)
+{
+    return ((const float*)X)[i];
+}
+template <> __device__ __forceinline__ float ld1<DT_F16>(const void* X, size_t i)
+{
+    return __half2float(((const __half*)X)[i]);
+}
+template <> __device__ __forceinline__ float ld1<DT_U16>(const void* X, size_t i)
+{
+    return (float)((const uint16_t*)X)[i] * (1.0f / 65536.0f);  // exact
+}
+
+// four consecutive bands [band0, band0+4) of one pixel row; bands >= b read 0
+template <int DT>
+__device__ __forceinline__ f4 ld4(const void* X, size_t row, int band0, int b)
+{
+    f4 v;
+    if (band0 + 4 <= b && (b & 3) == 0) {
+        const size_t i = row + band0;
+        if (DT == DT_F32) {
+            v = *(const f4*)((const float*)X + i);
+        } else if (DT == DT_F16) {
+            const uint2 u = *(const uint2*)((const __half*)X + i);
+            const __half2 h0 = *(const __half2*)&u.x, h1 = *(const __half2*)&u.y;
+            const float2 a = __half22float2(h0), c = __half22float2(h1);
+            v = f4{a.x, a.y, c.x, c.y};
+        } else {
+            const uint2 u = *(const uint2*)((const uint16_t*)X + i);
+            const float s = 1.0f / 65536.0f;
+            v = f4{(float)(u.x & 0xffffu) * s, (float)(u.x >> 16) * s,
+                   (float)(u.y & 0xffffu) * s, (float)(u.y >> 16) * s};
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (band0 + q < b) ? ld1<DT>(X, row + band0 + q) : 0.0f;
+    }
+    return v;
+}
+
+__device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile I <= J
+{
+    return (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
+}
+
+// ============================================================================
+// Gram: per line, mean and centred covariance (Sec. III-C, Eqs. (18)-(19)).
+//
+// One wave computes a 64x64 block ("macro tile", 4x4 tiles of 16 bands) of
+// the upper triangle of the band x band Gram matrix of one line.  Pixels are
+// the contraction index.  Data are shifted by s = the FP32 mean of the first
+// min(64, p) pixels of each band (identical in every wave), products are
+// accumulated on FP32 MFMA over 64-pixel chunks, chunk partials are summed
+// in FP64, and the exact identity
+//     sum (x-mu)(x-mu)^T = sum (x-s)(x-s)^T - p (mu-s)(mu-s)^T
+// turns the shifted sums into the centred covariance.
+//
+// Grid: 8 * ceil(n/8) * nmacro one-wave blocks; block ids are spread so that
+// all macro tiles of one line run on the same XCD (consecutive block ids are
+// dispatched round-robin over the 8 XCDs) and share its L2.
+// ============================================================================
+template <int DT>
+__global__ __launch_bounds__(64) void k_gram(const void* __restrict__ X, int n, int p, int b,
+                                             int NT, int nmacro, double* __restrict__ stats,
+                                             long long E)
+{
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7;
+    const int kk = bid >> 3;
+    const int ll = kk / nmacro;
+    int m = kk - ll * nmacro;
+    const int line = ll * 8 + xcd;
+    if (line >= n) return;
+    const int MT = (NT + 3) >> 2;
+    int MI = 0;
+    while (m >= MT - MI) {
+        m -= MT - MI;
+        ++MI;
+    }
+    const int MJ = MI + m;
+    const bool dg = (MI == MJ);
+    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const size_t lbase = (size_t)line * p * b;
+
+    int brow[4], bcol[4];
+    bool trow[4], tcol[4];  // tile exists
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        brow[q] = 16 * (4 * MI + q) + c;
+        bcol[q] = 16 * (4 * MJ + q) + c;
+        trow[q] = (4 * MI + q) < NT;
+        tcol[q] = (4 * MJ + q) < NT;
+    }
+
+    // shift: FP32 mean of the first min(64, p) pixels
+    const int p0 = p < 64 ? p : 64;
+    float srow[4], scol[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float s = 0.f, t = 0.f;
+        for (int k = g; k < p0; k += 4) {
+            const size_t r = lbase + (size_t)k * b;
+            if (brow[q] < b) s += ld1<DT>(X, r + brow[q]);
+            if (!dg && bcol[q] < b) t += ld1<DT>(X, r + bcol[q]);
+        }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        srow[q] = s / (float)p0;
+        scol[q] = dg ? srow[q] : t / (float)p0;
+    }
+
+    double S[4][4][4];
+    double sr[4], sc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        sr[a] = 0.0;
+        sc[a] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S[a][q][i] = 0.0;
+    }
+
+    for (int k0 = 0; k0 < p; k0 += 64) {
+        f4 acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] = f4{0.f, 0.f, 0.f, 0.f};
+        const int kend = (p - k0) < 64 ? (p - k0) : 64;
+        for (int ks = 0; ks < kend; ks += 4) {
+            const int pix = k0 + ks + g;
+            const bool ok = (ks + g) < kend;
+            const size_t r = lbase + (size_t)pix * b;
+            float av[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                av[q] = (ok && brow[q] < b) ? ld1<DT>(X, r + brow[q]) - srow[q] : 0.f;
+                if (dg)
+                    bv[q] = av[q];
+                else
+                    bv[q] = (ok && bcol[q] < b) ? ld1<DT>(X, r + bcol[q]) - scol[q] : 0.f;
+                sr[q] += (double)av[q];
+                sc[q] += (double)bv[q];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (trow[a] && tcol[q] && (!dg || a <= q)) acc[a][q] = mfma(av[a], bv[q], acc[a][q]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) S[a][q][i] += (double)acc[a][q][i];
+    }
+
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sr[q] += __shfl_xor(sr[q], 16);
+        sr[q] += __shfl_xor(sr[q], 32);
+        sc[q] += __shfl_xor(sc[q], 16);
+        sc[q] += __shfl_xor(sc[q], 32);
+    }
+    const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
+    double* ls = stats + (size_t)line * E;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!(trow[a] && tcol[q] && (!dg || a <= q))) continue;
+            double o[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double srho = __shfl(sr[a], 4 * g + i);  // sum of row band 16I+4g+i
+                o[i] = (S[a][q][i] - srho * sc[q] * inv_p) * inv_p1;
+            }
+            double* dst = ls + tile_u(4 * MI + a, 4 * MJ + q, NT) * 256 + lane * 4;
+            *(double2*)dst = double2{o[0], o[1]};
+            *(double2*)(dst + 2) = double2{o[2], o[3]};
+        }
+    }
+    if (dg && g == 0) {
+        const long long ntU = (long long)NT * (NT + 1) / 2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (trow[q]) ls[ntU * 256 + brow[q]] = (brow[q] < b) ? (double)srow[q] + sr[q] * inv_p : 0.0;
+    }
+}
+
+// ============================================================================
+// Exponential moving average as a chunked linear-recurrence scan
+// (Sec. III-C, Eqs. (20)-(21)).  With a_l = 1 for the stream's first line and
+// a_l = alpha afterwards, C_l = (1-a_l) C_{l-1} + a_l S_l for every entry of
+// the packed statistics.  Pass 1 runs the recurrence inside each segment from
+// a zero carry; pass 2 walks the segments to produce the carry entering each
+// segment; the Cholesky kernel adds D_l * carry, D_l = prod_{segment start..l}
+// (1-a_j), to obtain the full background of line l.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_scan_local(double* __restrict__ stats, long long E, int n,
+                                                    int seg, long long t0, double alpha)
+{
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= E) return;
+    const int l0 = blockIdx.y * seg;
+    const int l1 = (l0 + seg) < n ? (l0 + seg) : n;
+    double* ptr = stats + e;
+    double acc = 0.0;
+    int l = l0;
+    for (; l + 8 <= l1; l += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = ptr[(size_t)(l + q) * E];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double a = (t0 + l + q == 0) ? 1.0 : alpha;
+            acc = (1.0 - a) * acc + a * v[q];
+            v[q] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ptr[(size_t)(l + q) * E] = v[q];
+    }
+    for (; l < l1; ++l) {
+        const double a = (t0 + l == 0) ? 1.0 : alpha;
+        acc = (1.0 - a) * acc + a * ptr[(size_t)l * E];
+        ptr[(size_t)l * E] = acc;
+    }
+}
+
+__device__ __forceinline__ double seg_decay(long long t0, int l0, int l1, double alpha)
+{
+    double P = 1.0;
+    for (int l = l0; l < l1; ++l) P *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
+    return P;
+}
+
+__global__ __launch_bounds__(256) void k_scan_carry(const double* __restrict__ stats,
+                                                    double* __restrict__ carry,
+                                                    double* __restrict__ state, long long E, int n,
+                                                    int seg, long long t0, double alpha)
+{
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= E) return;
+    double cv = state[e];
+    const int nseg = (n + seg - 1) / seg;
+    for (int gs = 0; gs < nseg; ++gs) {
+        carry[(size_t)gs * E + e] = cv;
+        const int l0 = gs * seg;
+        const int l1 = (l0 + seg) < n ? (l0 + seg) : n;
+        cv = seg_decay(t0, l0, l1, alpha) * cv + stats[(size_t)(l1 - 1) * E + e];
+    }
+    state[e] = cv;
+}
+
+// ============================================================================
+// Cholesky of A_t = K_t + eps I, inverse factor M = L^{-1}, 1-norm condition
+// estimate (Sec. III-D).
+//
+// One workgroup per line.  The lower triangle of A is held in registers as
+// 16x16 tiles spread round-robin over the waves (tile s = I(I+1)/2 + J of
+// wave s % NW).  A tile slot holds A_IJ^T until its column is factored, then
+// L_IJ^T (panel), then the accumulator T_IJ of the inverse, finally M_IJ.
+// Right-looking blocked algorithm, for each block column K:
+//   1. the 16x16 diagonal block is factored and inverted by one wave with
+//      lane broadcasts;
+//   2. panel L_IK^T = L_KK^{-1} A_IK^T and inverse row M_KJ = L_KK^{-1} T_KJ;
+//   3. trailing update A_IJ^T -= L_JK L_IK^T and T_IJ -= L_IK M_KJ,
+// all on MFMA (FP32, or FP64 for the re-factor pass).  The condition number
+// estimate is ||A||_1 times Hager's estimate of ||A^{-1}||_1 (the LAPACK
+// xLACN2 iteration), applying A^{-1} = M^T M with the register tiles.
+//
+// The FP32 pass flags lines whose estimate exceeds the threshold (or whose
+// factorisation met a non-positive pivot); the FP64 instantiation then
+// re-factors only those lines.  Output: M^T tiles (FP32, accumulator layout,
+// the operand form the score kernel needs), mu_t (FP32), flags, estimate.
+// ============================================================================
+__device__ __forceinline__ float bcast(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double bcast(double v, int l)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NT> struct CholLds {
+    float part[NT * (NT + 1) / 2 * 32];  // per-tile partial sums (norms, mat-vecs)
+    float vec[4][16 * NT];                // x, y, z, scratch vectors
+    float red[64];
+};
+
+template <class T, int NT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ stats,
+                                                  const double* __restrict__ carry, long long E, int n,
+                                                  int seg, long long t0, double alpha, double eps, int b,
+                                                  float* __restrict__ Mt, float* __restrict__ mu32,
+                                                  int* __restrict__ flags, float* __restrict__ cond,
+                                                  double threshold, int want_cond, int force,
+                                                  unsigned long long* __restrict__ counters)
+{
+    typedef typename VT<T>::v V;
+    constexpr int NTL = NT * (NT + 1) / 2;
+    constexpr int SLOTS = (NTL + NW - 1) / NW;
+    constexpr bool FB = std::is_same<T, double>::value;
+    constexpr int BP = 16 * NT;
+    const int line = blockIdx.x;
+    if (line >= n) return;
+    // the FP64 instantiation factors every line (force) or the lines the FP32 pass flagged
+    if (FB && !force && !(flags[line] & FLAG_NEED_FP64)) return;  // uniform for the workgroup
+
+    __shared__ __attribute__((aligned(32))) T diag_s[16 * 17];
+    __shared__ __attribute__((aligned(32))) T xt_s[16 * 17];
+    __shared__ __attribute__((aligned(32))) T panel_s[NT * 256];
+    __shared__ __attribute__((aligned(32))) T mrow_s[NT * 256];
+    __shared__ __attribute__((aligned(16))) CholLds<NT> aux;
+    __shared__ int fail_s;
+
+    const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63,
+              g = lane >> 4, c = lane & 15;
+    const int gseg = line / seg, l0 = gseg * seg;
+    double D = 1.0;
+    for (int l = l0; l <= line; ++l) D *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
+    if (tid == 0) fail_s = 0;
+
+    // ---- load A_IJ^T = (K_loc + D carry)_{JI} (+ eps on the diagonal)
+    V A[SLOTS];
+    int tI[SLOTS], tJ[SLOTS];
+    const double* st = stats + (size_t)line * E;
+    const double* cr = carry + (size_t)gseg * E;
+#pragma unroll
+    for (int j = 0; j < SLOTS; ++j) {
+        const int s = j * NW + w;
+        int I = -1, J = -1;
+        if (s < NTL) {
+            I = (int)((__fsqrt_rn(8.0f * s + 1.0f) - 1.0f) * 0.5f);
+            while ((I + 1) * (I + 2) / 2 <= s) ++I;
+            while (I * (I + 1) / 2 > s) --I;
+            J = s - I * (I + 1) / 2;
+        }
+        tI[j] = I;
+        tJ[j] = J;
+        if (I >= 0) {
+            const long long u = tile_u(J, I, NT) * 256;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = rowof<T>(g, i);  // stored in the FP32 accumulator layout
+                const long long o = u + (16 * (row >> 2) + c) * 4 + (row & 3);
+                double v = st[o] + D * cr[o];
+                const int rb = 16 * J + row, cb = 16 * I + c;
+                if (rb == cb) v += eps;
+                if (rb >= b || cb >= b) v = (rb == cb) ? 1.0 : 0.0;
+                A[j][i] = (T)v;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) A[j][i] = (T)0;
+        }
+    }
+    if (!FB || force) {
+        const long long ntU = NTL;
+        for (int q = tid; q < BP; q += NW * 64) {
+            const double v = st[ntU * 256 + q] + D * cr[ntU * 256 + q];
+            mu32[(size_t)line * BP + q] = (q < b) ? (float)v : 0.0f;
+        }
+    }
+
+    // ---- ||A||_1 (row sums of |A| over the real bands), deterministic
+    float anorm = 0.f;
+    if (want_cond) {
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            if (tI[j] < 0) continue;
+            const int s = tI[j] * (tI[j] + 1) / 2 + tJ[j];
+            // slot element (row, c) is A[16J+row][16I+c]
+            float ra = 0.f;  // row 16I+c of A_IJ: sum over i, then over g
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ra += fabsf((float)A[j][i]);
+            ra += __shfl_xor(ra, 16);
+            ra += __shfl_xor(ra, 32);
+            float rb[4];  // rows 16J+row of A_JI (mirror), sum over c
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = (tI[j] != tJ[j]) ? fabsf((float)A[j][i]) : 0.f;
+                v += __shfl_xor(v, 8);
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 1);
+                rb[i] = v;
+            }
+            if (g == 0) aux.part[s * 32 + c] = ra;
+            if (c == 0)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) aux.part[s * 32 + 16 + rowof<T>(g, i)] = rb[i];
+        }
+        __syncthreads();
+        float mx = 0.f;
+        for (int q = tid; q < BP; q += NW * 64) {
+            const int R = q >> 4, r = q & 15;
+            float sum = 0.f;
+            for (int J = 0; J <= R; ++J) sum += aux.part[(R * (R + 1) / 2 + J) * 32 + r];
+            for (int I = R + 1; I < NT; ++I) sum += aux.part[(I * (I + 1) / 2 + R) * 32 + 16 + r];
+            if (q < b) mx = fmaxf(mx, sum);
+        }
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        if (lane == 0) aux.red[w] = mx;
+        __syncthreads();
+        mx = 0.f;
+        for (int q = 0; q < NW; ++q) mx = fmaxf(mx, aux.red[q]);
+        anorm = mx;
+        __syncthreads();
+    }
+
+    // ---- blocked factorisation and inversion
+    for (int K = 0; K < NT; ++K) {
+        // 1a. owner of the diagonal tile publishes A_KK (slot holds A_KK^T)
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j)
+            if (tI[j] == K && tJ[j] == K)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) diag_s[c * 17 + rowof<T>(g, i)] = A[j][i];
+        __syncthreads();
+        // 1b. one wave: L_KK (lanes = rows) and X = L_KK^{-1} (lanes = columns)
+        if (w == 0) {
+            const int r = lane & 15;
+            T a[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) a[q] = (q <= r) ? diag_s[r * 17 + q] : (T)0;
+            int bad = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const T akk = bcast(a[k], k);
+                if (akk <= (T)0) bad = 1;
+                const T dk = sqrt(akk);
+                const T inv = (T)1 / dk;
+                const T lrk = (r > k) ? a[k] * inv : ((r == k) ? dk : (T)0);
+                a[k] = lrk;
+#pragma unroll
+                for (int q = k + 1; q < 16; ++q) {
+                    const T lqk = bcast(lrk, q);
+                    if (r >= q) a[q] -= lrk * lqk;
+                }
+            }
+            T x[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                T s = (q == r) ? (T)1 : (T)0;
+#pragma unroll
+                for (int k = 0; k < q; ++k) s -= bcast(a[k], q) * x[k];
+                x[q] = s / bcast(a[q], q);
+            }
+            if (lane < 16)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) xt_s[q * 17 + lane] = x[q];  // xt[row][col] = X[row][col]
+            if (bad && lane == 0) fail_s = 1;
+        }
+        __syncthreads();
+        // 2. panel and inverse row
+        V xinvT;  // X^T in accumulator layout: element (row, c) = X[c][row]
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xinvT[i] = xt_s[c * 17 + rowof<T>(g, i)];
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            if (tJ[j] == K && tI[j] > K) {
+                V z = {};
+                A[j] = mma_xty(z, xinvT, A[j]);  // L_IK^T = X A_IK^T
+                *(V*)&panel_s[tI[j] * 256 + lane * 4] = A[j];
+            } else if (tI[j] == K && tJ[j] < K) {
+                V z = {};
+                A[j] = mma_xty(z, xinvT, A[j]);  // M_KJ = X T_KJ
+                *(V*)&mrow_s[tJ[j] * 256 + lane * 4] = A[j];
+            } else if (tI[j] == K && tJ[j] == K) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) A[j][i] = xt_s[rowof<T>(g, i) * 17 + c];  // M_KK = X
+                *(V*)&mrow_s[K * 256 + lane * 4] = A[j];
+            }
+        }
+        __syncthreads();
+        // 3. trailing update of A and update of the inverse accumulators
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            const int I = tI[j], J = tJ[j];
+            if (I <= K) continue;
+            if (J > K) {
+                V xp = *(const V*)&panel_s[J * 256 + lane * 4];
+                const V yp = *(const V*)&panel_s[I * 256 + lane * 4];
+                xp = -xp;
+                A[j] = mma_xty(A[j], xp, yp);  // A_IJ^T -= L_JK L_IK^T
+            } else {
+                V xp = *(const V*)&panel_s[I * 256 + lane * 4];
+                const V yp = *(const V*)&mrow_s[J * 256 + lane * 4];
+                xp = -xp;
+                if (J == K) {
+                    V z = {};
+                    A[j] = mma_xty(z, xp, yp);  // T_IK = -L_IK M_KK
+                } else {
+                    A[j] = mma_xty(A[j], xp, yp);  // T_IJ -= L_IK M_KJ
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int fail = fail_s;
+
+    // ---- M^T tiles for the score kernel, in the FP32 accumulator layout
+    //      (element (r,q) of M_JK goes to lane 16(q/4)+r, register q%4)
+    {
+        float* dstl = Mt + (size_t)line * NTL * 256;
+        const bool nanout = FB && fail;
+#pragma unroll
+        for (int j = 0; j < SLOTS; ++j) {
+            if (tI[j] < 0) continue;
+            const int s = tI[j] * (tI[j] + 1) / 2 + tJ[j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int off = 64 * (c >> 2) + 4 * rowof<T>(g, i) + (c & 3);
+                dstl[(size_t)s * 256 + off] = nanout ? __builtin_nanf("") : (float)A[j][i];
+            }
+        }
+    }
+
+    // ---- Hager / Higham estimate of ||A^{-1}||_1 with A^{-1} = M^T M
+    float est = 0.f;
+    if (want_cond && !fail) {
+        float* xv = aux.vec[0];
+        float* yv = aux.vec[1];
+        float* zv = aux.vec[2];
+        float* sg = aux.vec[3];
+        const int NTH = NW * 64;
+        // y <- M x, then z <- M^T y : z = A^{-1} x (x in xv, result in zv)
+        auto apply = [&]() __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < SLOTS; ++j) {
+                if (tI[j] < 0) continue;
+                const int s = tI[j] * (tI[j] + 1) / 2 + tJ[j];
+                const float xc = xv[16 * tJ[j] + c];
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = (float)A[j][i] * xc;
+                    v[i] += __shfl_xor(v[i], 8);
+                    v[i] += __shfl_xor(v[i], 4);
+                    v[i] += __shfl_xor(v[i], 2);
+                    v[i] += __shfl_xor(v[i], 1);
+                }
+                if (c == 0)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) aux.part[s * 32 + rowof<T>(g, i)] = v[i];
+            }
+            __syncthreads();
+            for (int q = tid; q < BP; q += NTH) {
+                const int R = q >> 4, r = q & 15;
+                float sum = 0.f;
+                for (int J = 0; J <= R; ++J) sum += aux.part[(R * (R + 1) / 2 + J) * 32 + r];
+                yv[q] = sum;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < SLOTS; ++j) {
+                if (tI[j] < 0) continue;
+                const int s = tI[j] * (tI[j] + 1) / 2 + tJ[j];
+                float v = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v += (float)A[j][i] * yv[16 * tI[j] + rowof<T>(g, i)];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (g == 0) aux.part[s * 32 + 16 + c] = v;
+            }
+            __syncthreads();
+            for (int q = tid; q < BP; q += NTH) {
+                const int Jc = q >> 4, cc = q & 15;
+                float sum = 0.f;
+                for (int I = Jc; I < NT; ++I) sum += aux.part[(I * (I + 1) / 2 + Jc) * 32 + 16 + cc];
+                zv[q] = (q < b) ? sum : 0.f;
+            }
+            __syncthreads();
+        };
+        // block reductions over the b real entries of zv
+        auto norm1 = [&]() __attribute__((always_inline)) -> float {
+            float s = 0.f;
+            for (int q = tid; q < b; q += NTH) s += fabsf(zv[q]);
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) aux.red[w] = s;
+            __syncthreads();
+            float t = 0.f;
+            for (int q = 0; q < NW; ++q) t += aux.red[q];
+            __syncthreads();
+            return t;
+        };
+        auto argmax_abs = [&]() __attribute__((always_inline)) -> int {  // first index of the largest |zv|
+            float best = -1.f;
+            int bi = 0;
+            for (int q = tid; q < b; q += NTH) {
+                const float v = fabsf(zv[q]);
+                if (v > best) { best = v; bi = q; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const float ob = __shfl_xor(best, o);
+                const int oi = __shfl_xor(bi, o);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (lane == 0) {
+                aux.red[w] = best;
+                aux.red[32 + w] = __int_as_float(bi);
+            }
+            __syncthreads();
+            float bb = -1.f;
+            int ii = 0;
+            for (int q = 0; q < NW; ++q) {
+                const float v = aux.red[q];
+                const int iq = __float_as_int(aux.red[32 + q]);
+                if (v > bb || (v == bb && iq < ii)) { bb = v; ii = iq; }
+            }
+            __syncthreads();
+            return ii;
+        };
+        // x = 1/b
+        for (int q = tid; q < BP; q += NTH) xv[q] = (q < b) ? 1.0f / (float)b : 0.f;
+        __syncthreads();
+        apply();
+        est = norm1();
+        if (b > 1) {
+            // sign vector of y (ties to +1), then z = A^{-1} sign
+            for (int q = tid; q < BP; q += NTH) {
+                const float sv = (zv[q] >= 0.f) ? 1.f : -1.f;
+                sg[q] = sv;
+                xv[q] = (q < b) ? sv : 0.f;
+            }
+            __syncthreads();
+            apply();
+            int jx = argmax_abs();
+            for (int it = 2; it <= 5; ++it) {
+                for (int q = tid; q < BP; q += NTH) xv[q] = (q == jx) ? 1.f : 0.f;
+                __syncthreads();
+                apply();
+                const float estold = est;
+                const float e2 = norm1();
+                est = fmaxf(est, e2);
+                // repeated sign vector?
+                int diff = 0;
+                for (int q = tid; q < b; q += NTH) diff |= (((zv[q] >= 0.f) ? 1.f : -1.f) != sg[q]);
+                diff = __syncthreads_or(diff);
+                if (!diff || e2 <= estold) break;
+                for (int q = tid; q < BP; q += NTH) {
+                    const float sv = (zv[q] >= 0.f) ? 1.f : -1.f;
+                    sg[q] = sv;
+                    xv[q] = (q < b) ? sv : 0.f;
+                }
+                __syncthreads();
+                apply();
+                const float zlast = fabsf(zv[jx]);
+                const int jn = argmax_abs();
+                if (zlast == fabsf(zv[jn])) break;
+                jx = jn;
+            }
+            // alternating-sign safeguard
+            for (int q = tid; q < BP; q += NTH)
+                xv[q] = (q < b) ? ((q & 1) ? -1.f : 1.f) * (1.f + (float)q / (float)(b - 1)) : 0.f;
+            __syncthreads();
+            apply();
+            const float tmp = 2.f * norm1() / (3.f * (float)b);
+            est = fmaxf(est, tmp);
+        }
+        est *= anorm;
+    }
+
+    if (tid == 0) {
+        const bool fin = want_cond && !fail && isfinite(est);
+        int f;
+        if (!FB) {
+            f = 0;
+            if (fail || threshold <= 0.0 || (want_cond && (double)est > threshold)) f |= FLAG_NEED_FP64;
+            cond[line] = fail ? __builtin_inff() : (want_cond ? est : 0.f);
+            if (!(f & FLAG_NEED_FP64) && fin) atomicMax((unsigned int*)&counters[2], __float_as_uint(est));
+        } else {
+            f = (force ? 0 : flags[line]) | FLAG_FP64_DONE | (fail ? FLAG_NOTPD : 0);
+            cond[line] = fail ? __builtin_inff() : est;
+            if (fin) atomicMax((unsigned int*)&counters[2], __float_as_uint(est));
+            atomicAdd(&counters[0], 1ull);
+            if (fail) atomicAdd(&counters[1], 1ull);
+        }
+        flags[line] = f;
+    }
+}
+
+// ============================================================================
+// Score (Sec. III-D, Eqs. (22)-(23)): for each pixel, r = x - mu_t, m = M r
+// with M = L_t^{-1} lower triangular, delta = ||m||.  Y_J = sum_{K<=J} M_JK R_K
+// for 16-pixel column tiles R_K (bands 16K..16K+15) on FP32 MFMA: the M^T
+// tiles are read in operand form and R_K is four consecutive bands of one
+// pixel per lane, which is exactly the accumulator-layout operand of X^T Y.
+// Each wave scores PT tiles of 16 pixels; a workgroup is 4 waves.
+// ============================================================================
+template <int NT, int DT>
+__global__ __launch_bounds__(256) void k_score(const void* __restrict__ X, const float* __restrict__ Mt,
+                                               const float* __restrict__ mu32, int n, int p, int b,
+                                               int ngrp, float* __restrict__ out)
+{
+    constexpr int NTL = NT * (NT + 1) / 2;
+    constexpr int PT = SCORE_PT;
+    const int line = blockIdx.x / ngrp, grp = blockIdx.x - line * ngrp;
+    if (line >= n) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const int pix0 = (grp * 4 + w) * PT * 16;
+    if (pix0 >= p) return;  // wave-uniform; the kernel has no barrier
+    const float* mu = mu32 + (size_t)line * 16 * NT;
+    const float* Ml = Mt + (size_t)line * NTL * 256 + lane * 4;
+    const size_t lrow = (size_t)line * p;
+
+    f4 acc[NT][PT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int t = 0; t < PT; ++t) acc[J][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int K = 0; K < NT; ++K) {
+        const int band0 = 16 * K + 4 * g;
+        const f4 m4 = *(const f4*)(mu + band0);
+        f4 y[PT];
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int pix = pix0 + 16 * t + c;
+            if (pix < p) {
+                y[t] = ld4<DT>(X, (lrow + pix) * (size_t)b, band0, b) - m4;
+                // padded bands read 0 and have mu 0
+            } else {
+                y[t] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+#pragma unroll
+        for (int J = K; J < NT; ++J) {
+            const f4 xm = *(const f4*)(Ml + (J * (J + 1) / 2 + K) * 256);
+#pragma unroll
+            for (int t = 0; t < PT; ++t) acc[J][t] = mma_xty(acc[J][t], xm, y[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+        float ss = 0.f;
+#pragma unroll
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ss += acc[J][t][i] * acc[J][t][i];
+        ss += __shfl_xor(ss, 16);
+        ss += __shfl_xor(ss, 32);
+        const int pix = pix0 + 16 * t + c;
+        if (g == 0 && pix < p) out[lrow + pix] = sqrtf(ss);
+    }
+}
+
+// ============================================================================
+// Line normalisation (Sec. III-E, Eq. (24)): population mean and deviation of
+// the p scores of each line in FP64, (delta - mean) / std, 0 when std is 0.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ d, float* __restrict__ dn,
+                                                   int n, int p)
+{
+    const int line = blockIdx.x;
+    if (line >= n) return;
+    __shared__ double red[256];
+    const float* x = d + (size_t)line * p;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < p; i += 256) s += (double)x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double mean = red[0] / (double)p;
+    __syncthreads();
+    double v = 0.0;
+    for (int i = threadIdx.x; i < p; i += 256) {
+        const double q = (double)x[i] - mean;
+        v += q * q;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double sd = sqrt(red[0] / (double)p);
+    for (int i = threadIdx.x; i < p; i += 256)
+        dn[(size_t)line * p + i] =
+            (sd > 0.0) ? (float)(((double)x[i] - mean) / sd) : (sd == 0.0 ? 0.0f : (float)sd);
+}
+
+// ============================================================================
+// Labels (Sec. III-E, Eq. (25)): y = [delta_N >= tau]; lines inside the
+// warm-up buffer give 0.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_labels(const float* __restrict__ dn, int n, int p, float tau,
+                                                long long t0, int warmup, unsigned char* __restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (long long)n * p) return;
+    const long long line = t0 + i / p;
+    out[i] = (line >= warmup && dn[i] >= tau) ? 1 : 0;
+}
+
+// ============================================================================
+// host-side launchers
+// ============================================================================
+static int gram_macros(int NT)
+{
+    const int MT = (NT + 3) / 4;
+    return MT * (MT + 1) / 2;
+}
+
+hipError_t launch_gram(int dtype, const void* X, int n, int p, int b, int NT, double* stats,
+                       long long E, hipStream_t s)
+{
+    const int nm = gram_macros(NT);
+    const long long nblk = (long long)((n + 7) / 8) * 8 * nm;
+    dim3 grid((unsigned)nblk), block(64);
+    switch (dtype) {
+    case DT_F32: hipLaunchKernelGGL(k_gram<DT_F32>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
+    case DT_F16: hipLaunchKernelGGL(k_gram<DT_F16>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
+    default: hipLaunchKernelGGL(k_gram<DT_U16>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_local(double* stats, long long E, int n, int seg, long long t0, double alpha,
+                             hipStream_t s)
+{
+    const int nseg = (n + seg - 1) / seg;
+    dim3 g1((unsigned)((E + 255) / 256), (unsigned)nseg);
+    hipLaunchKernelGGL(k_scan_local, g1, dim3(256), 0, s, stats, E, n, seg, t0, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_carry(const double* stats, double* carry, double* state, long long E, int n, int seg,
+                             long long t0, double alpha, hipStream_t s)
+{
+    dim3 g2((unsigned)((E + 255) / 256));
+    hipLaunchKernelGGL(k_scan_carry, g2, dim3(256), 0, s, stats, carry, state, E, n, seg, t0, alpha);
+    return hipGetLastError();
+}
+
+template <class T, int NT> constexpr int chol_waves()
+{
+    return NT <= 6 ? 4 : 8;
+}
+
+template <class T, int NT>
+static void chol_one(const double* stats, const double* carry, long long E, int n, int seg, long long t0,
+                     double alpha, double eps, int b, float* Mt, float* mu32, int* flags, float* cond,
+                     double thr, int want, int force, unsigned long long* ctr, hipStream_t s)
+{
+    constexpr int NW = chol_waves<T, NT>();
+    hipLaunchKernelGGL((k_chol<T, NT, NW>), dim3(n), dim3(NW * 64), 0, s, stats, carry, E, n, seg, t0,
+                       alpha, eps, b, Mt, mu32, flags, cond, thr, want, force, ctr);
+}
+
+template <class T, int... NTs>
+static void chol_dispatch(std::integer_sequence<int, NTs...>, int NT, const double* stats,
+                          const double* carry, long long E, int n, int seg, long long t0, double alpha,
+                          double eps, int b, float* Mt, float* mu32, int* flags, float* cond,
+                          double thr, int want, int force, unsigned long long* ctr, hipStream_t s)
+{
+    ((NT == NTs + 1 ? chol_one<T, NTs + 1>(stats, carry, E, n, seg, t0, alpha, eps, b, Mt, mu32, flags,
+                                           cond, thr, want, force, ctr, s)
+                    : void()),
+     ...);
+}
+
+hipError_t launch_chol(int fp64, int force, int NT, const double* stats, const double* carry, long long E,
+                       int n, int seg, long long t0, double alpha, double eps, int b, float* Mt, float* mu32,
+                       int* flags, float* cond, double thr, int want_cond, unsigned long long* ctr,
+                       hipStream_t s)
+{
+    if (NT < 1 || NT > MAX_NT) return hipErrorInvalidValue;
+    if (fp64)
+        chol_dispatch<double>(std::make_integer_sequence<int, MAX_NT>(), NT, stats, carry, E, n, seg, t0,
+                              alpha, eps, b, Mt, mu32, flags, cond, thr, want_cond, force, ctr, s);
+    else
+        chol_dispatch<float>(std::make_integer_sequence<int, MAX_NT>(), NT, stats, carry, E, n, seg, t0,
+                             alpha, eps, b, Mt, mu32, flags, cond, thr, want_cond, 0, ctr, s);
+    return hipGetLastError();
+}
+
+template <int NT, int DT>
+static void score_one(const void* X, const float* Mt, const float* mu32, int n, int p, int b, float* out,
+                      hipStream_t s)
+{
+    const int per = 4 * SCORE_PT * 16;
+    const int ngrp = (p + per - 1) / per;
+    hipLaunchKernelGGL((k_score<NT, DT>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, X, Mt,
+                       mu32, n, p, b, ngrp, out);
+}
+
+template <int DT, int... NTs>
+static void score_dispatch(std::integer_sequence<int, NTs...>, int NT, const void* X, const float* Mt,
+                           const float* mu32, int n, int p, int b, float* out, hipStream_t s)
+{
+    ((NT == NTs + 1 ? score_one<NTs + 1, DT>(X, Mt, mu32, n, p, b, out, s) : void()), ...);
+}
+
+hipError_t launch_score(int dtype, int NT, const void* X, const float* Mt, const float* mu32, int n, int p,
+                        int b, float* out, hipStream_t s)
+{
+    if (NT < 1 || NT > MAX_NT) return hipErrorInvalidValue;
+    auto seq = std::make_integer_sequence<int, MAX_NT>();
+    switch (dtype) {
+    case DT_F32: score_dispatch<DT_F32>(seq, NT, X, Mt, mu32, n, p, b, out, s); break;
+    case DT_F16: score_dispatch<DT_F16>(seq, NT, X, Mt, mu32, n, p, b, out, s); break;
+    default: score_dispatch<DT_U16>(seq, NT, X, Mt, mu32, n, p, b, out, s); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_labels(const float* dn, int n, int p, float tau, long long t0, int warmup,
+                         unsigned char* out, hipStream_t s)
+{
+    const long long N = (long long)n * p;
+    hipLaunchKernelGGL(k_labels, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, dn, n, p, tau, t0,
+                       warmup, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalise(const float* d, float* dn, int n, int p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_normalise, dim3(n), dim3(256), 0, s, d, dn, n, p);
+    return hipGetLastError();
+}
+
+}  // namespace erx

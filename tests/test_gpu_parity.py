@@ -1,0 +1,332 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance (plain FP32 path): err_i = |delta_i - delta*_i| / max(delta*_i, 1)
+<= 1e-4 for every pixel, where delta* is the oracle's FP64 score of the same
+input.  The floor of 1 guards pixels sitting on the background mean.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def log(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def erx():
+    import paper_2408_14947_amd as m
+    m.load()
+    return m
+
+
+def rel_err(got, want):
+    got = np.asarray(got, np.float64)
+    return np.abs(got - want) / np.maximum(np.abs(want), 1.0)
+
+
+def run_gpu(erx, X, momentum=0.1, ridge=1e-5, chunks=None, **kw):
+    T, p, b = X.shape
+    det = erx.Detector(b, p, momentum, ridge, **kw)
+    Xd = X.cuda() if isinstance(X, torch.Tensor) else torch.as_tensor(X).cuda()
+    outs = []
+    bounds = chunks or [(0, T)]
+    for a, c in bounds:
+        det.push(Xd[a:c])
+        outs.append(det.scores().cpu().numpy())
+    torch.cuda.synchronize()
+    return np.concatenate(outs), det
+
+
+def storage_f64(X, storage):
+    return datagen.storage_to_float64(X, storage)
+
+
+CASES = [
+    # (bands, pixels, lines, block_lines, scan_lines)
+    (1, 2, 9, 4, 3),
+    (1, 63, 70, 32, 16),
+    (4, 63, 70, 2048, 64),
+    (16, 100, 130, 50, 16),
+    (17, 65, 66, 40, 7),
+    (33, 200, 100, 64, 64),
+    (100, 128, 80, 33, 10),
+    (108, 640, 150, 64, 16),
+    (224, 256, 70, 32, 16),
+    (250, 520, 24, 10, 4),
+    (300, 640, 20, 2048, 64),
+]
+
+
+@pytest.mark.parametrize("b,p,T,blk,seg", CASES)
+def test_parity_shapes(erx, b, p, T, blk, seg):
+    log(f"shape b={b} p={p} T={T} block_lines={blk} scan_lines={seg}")
+    scene = datagen.make_scene(11, b * 1000 + p, b, p, T)
+    X, _ = datagen.lines(scene, 0, T)
+    got, det = run_gpu(erx, X, block_lines=blk, scan_lines=seg)
+    want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
+    err = rel_err(got, want)
+    log(f"  max err {err.max():.3e}  fp64 re-factors {det.stats()['fp64_refactors']}")
+    assert err.max() <= TOL
+
+
+def test_parity_plain_108_full(erx):
+    """500 lines x 640 px x 108 bands (the single-stream 108-band workload)."""
+    sc = datagen.config_scenes(1)[0]
+    log(f"plain-108 full: {sc.lines} x {sc.pixels} x {sc.bands}")
+    X, _ = datagen.lines(sc, 0, sc.lines)
+    got, det = run_gpu(erx, X)
+    want = oracle.run(X.numpy(), sc.momentum, 1e-5)["delta"]
+    err = rel_err(got, want)
+    log(f"  max err {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() <= TOL
+
+
+def test_parity_long_scan_224_cut(erx):
+    """First 400 lines of the 20000 x 1024 x 224 drifting scan."""
+    sc = datagen.config_scenes(2, scale_lines=400)[0]
+    log("long-scan-224 cut: 400 x 1024 x 224")
+    X, _ = datagen.lines(sc, 0, 400)
+    got, det = run_gpu(erx, X, block_lines=256)
+    want = oracle.run(X.numpy(), sc.momentum, 1e-5)["delta"]
+    err = rel_err(got, want)
+    log(f"  max err {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() <= TOL
+
+
+@pytest.mark.parametrize("momentum", [1.0, 0.5, 0.01])
+def test_parity_momentum(erx, momentum):
+    log(f"momentum {momentum}")
+    sc = datagen.make_scene(12, 0, 64, 300, 90, momentum=momentum)
+    X, _ = datagen.lines(sc, 0, 90)
+    got, _ = run_gpu(erx, X, momentum=momentum, scan_lines=16)
+    want = oracle.run(X.numpy(), momentum, 1e-5)["delta"]
+    assert rel_err(got, want).max() <= TOL
+
+
+@pytest.mark.parametrize("storage,b", [("f16", 4), ("f16", 16), ("u16", 37), ("u16", 96)])
+def test_parity_storage_types(erx, storage, b):
+    log(f"storage {storage} b={b}")
+    kind = "gauss" if storage == "f16" else "mixture"
+    sc = datagen.make_scene(13, b, b, 257, 75, kind=kind, storage=storage)
+    X, _ = datagen.lines(sc, 0, 75)
+    got, _ = run_gpu(erx, X, dtype=storage, scan_lines=16)
+    want = oracle.run(storage_f64(X, storage), 0.1, 1e-5)["delta"]
+    assert rel_err(got, want).max() <= TOL
+
+
+def test_chunked_pushes_match_oracle(erx):
+    log("chunked pushes")
+    sc = datagen.make_scene(14, 0, 48, 128, 157)
+    X, _ = datagen.lines(sc, 0, 157)
+    want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
+    parts = [(0, 1), (1, 2), (2, 70), (70, 71), (71, 157)]
+    got, _ = run_gpu(erx, X, chunks=parts, block_lines=40, scan_lines=16)
+    assert rel_err(got, want).max() <= TOL
+
+
+def test_determinism(erx):
+    log("determinism")
+    sc = datagen.make_scene(15, 0, 96, 333, 77)
+    X, _ = datagen.lines(sc, 0, 77)
+    a, _ = run_gpu(erx, X, scan_lines=16)
+    b, _ = run_gpu(erx, X, scan_lines=16)
+    assert np.array_equal(a, b)
+
+
+def test_state_roundtrip_and_resume(erx):
+    log("state round trip")
+    sc = datagen.make_scene(16, 0, 40, 150, 60)
+    X, _ = datagen.lines(sc, 0, 60)
+    ora = oracle.Stream(40, 150, 0.1, 1e-5)
+    ora.push(X[:35].numpy())
+    t, mu, K = ora.state()
+    det = erx.Detector(40, 150, 0.1)
+    det.push(X[:35].cuda())
+    tg, mug, Kg = det.state()
+    assert tg == t == 35
+    # the GPU's state comes from FP32 products summed in FP64: entries agree to a
+    # few FP32 ulps of the largest entry
+    np.testing.assert_allclose(mug, mu, rtol=1e-6, atol=1e-6 * np.abs(mu).max())
+    np.testing.assert_allclose(Kg, K, rtol=1e-5, atol=1e-6 * np.abs(K).max())
+    # restore into a new handle from the oracle's state and continue
+    det2 = erx.Detector(40, 150, 0.1)
+    det2.set_state(t, mu, K)
+    det2.push(X[35:].cuda())
+    got = det2.scores().cpu().numpy()
+    want = ora.push(X[35:].numpy())["delta"]
+    assert rel_err(got, want).max() <= TOL
+    # reset
+    det2.set_state(0)
+    det2.push(X[:5].cuda())
+    assert rel_err(det2.scores().cpu().numpy(), oracle.run(X[:5].numpy(), 0.1)["delta"]).max() <= TOL
+
+
+def test_host_input_and_host_output(erx):
+    log("host input")
+    sc = datagen.make_scene(17, 0, 24, 90, 30)
+    X, _ = datagen.lines(sc, 0, 30)
+    det = erx.Detector(24, 90, 0.1, block_lines=7)
+    det.push(np.ascontiguousarray(X.numpy()))
+    got = det.scores_host()
+    assert rel_err(got, oracle.run(X.numpy(), 0.1)["delta"]).max() <= TOL
+
+
+def test_forced_fp64_refactor(erx):
+    log("threshold 0: every line re-factored in FP64")
+    sc = datagen.make_scene(18, 0, 120, 400, 40)
+    X, _ = datagen.lines(sc, 0, 40)
+    got, det = run_gpu(erx, X, fp64_cond_threshold=0.0, scan_lines=16)
+    want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
+    assert rel_err(got, want).max() <= TOL
+    st = det.stats()
+    assert st["fp64_refactors"] == 40
+    cond, flags = det.line_info()
+    assert np.all(flags & erx.FLAG_FP64_DONE)
+
+
+def ill_conditioned_stream(seed=19, T=30, p=256, b=32, pert=8):
+    """Integer-valued lines with a fixed rank-4 band structure plus sparse +-1
+    perturbations (condition number of K_t + eps I around 1e6).  Values are small
+    integers and the first 64 pixels are symmetric about an integer mean, so the
+    FP32 Gram of the shifted data is exact and only the factorisation precision
+    matters."""
+    rng = np.random.default_rng(seed)
+    X = np.empty((T, p, b), np.float32)
+    C0 = rng.integers(0, 5, size=(4, b))
+    for t in range(T):
+        x = rng.integers(0, 16, size=(p, 4)) @ C0
+        idx = rng.integers(0, p, size=(pert, b))
+        for j in range(b):
+            x[idx[:, j], j] += rng.choice([-1, 1], size=pert)
+        m = np.round(x[:64].mean(0))
+        x[32:64] = 2 * m - x[:32]
+        X[t] = x
+    return X
+
+
+def test_ill_conditioned_lines_take_fp64(erx):
+    log("ill-conditioned stream")
+    X = ill_conditioned_stream()
+    want = oracle.run(X, 0.1, float(np.float32(1e-5)))["delta"]
+    got, det = run_gpu(erx, torch.from_numpy(X), scan_lines=8, fp64_cond_threshold=1e6)
+    cond, flags = det.line_info()
+    st = det.stats()
+    err = rel_err(got, want).max()
+    got32, det32 = run_gpu(erx, torch.from_numpy(X), scan_lines=8, fp64_cond_threshold=math.inf)
+    err32 = rel_err(got32, want).max()
+    log(f"  fp64 re-factors {st['fp64_refactors']}/30, max cond {st['max_cond']:.3g}, "
+        f"err {err:.3e}; FP32-only err {err32:.3e}")
+    assert st["fp64_refactors"] == 30 and np.all(flags & erx.FLAG_FP64_DONE) and cond.min() > 1e6
+    assert det32.stats()["fp64_refactors"] == 0
+    assert err <= TOL
+    assert err32 > 2 * err
+
+
+def test_fp32_factorisation_with_fallback_108(erx):
+    """FP32 Cholesky with the condition-estimate fallback (threshold 1e6) on the
+    500 x 640 x 108 workload stays within the FP32 bound."""
+    sc = datagen.config_scenes(1)[0]
+    log("FP32 factorisation + fallback, plain-108")
+    X, _ = datagen.lines(sc, 0, sc.lines)
+    got, det = run_gpu(erx, X, fp64_cond_threshold=1e6)
+    want = oracle.run(X.numpy(), sc.momentum, 1e-5)["delta"]
+    err = rel_err(got, want)
+    log(f"  max err {err.max():.3e}; fp64 re-factors {det.stats()['fp64_refactors']}")
+    assert err.max() <= TOL
+
+
+def test_condition_estimate_tracks_lapack(erx):
+    """The 1-norm estimate lies between kappa_1/3 and kappa_1 (Hager/Higham bound)."""
+    log("condition estimate")
+    sc = datagen.make_scene(20, 0, 64, 300, 20)
+    X, _ = datagen.lines(sc, 0, 20)
+    _, det = run_gpu(erx, X, scan_lines=8)
+    cond, _ = det.line_info()
+    r = oracle.run(X.numpy(), 0.1, 1e-5, history=True)
+    for t in (0, 5, 19):
+        A = r["K_hist"][t] + 1e-5 * np.eye(64)
+        k1 = np.linalg.norm(A, 1) * np.linalg.norm(np.linalg.inv(A), 1)
+        assert k1 / 3.5 <= cond[t] <= k1 * 1.01, (t, cond[t], k1)
+
+
+def test_not_positive_definite(erx):
+    log("not positive definite lines")
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((6, 40, 8)).astype(np.float32)
+    X[3:, :, 2] = 0.5
+    got, det = run_gpu(erx, torch.from_numpy(X), momentum=1.0, ridge=0.0)
+    want = oracle.run(X, 1.0, 0.0)
+    cond, flags = det.line_info()
+    assert list((flags & erx.FLAG_NOTPD) > 0) == list(want["notpd"].astype(bool))
+    assert np.isnan(got[3:]).all() and np.isfinite(got[:3]).all()
+    assert rel_err(got[:3], want["delta"][:3]).max() <= TOL
+    with pytest.raises(erx.ErxError):
+        det.scores_host(allow_notpd=False)
+
+
+def test_nan_input_propagates_forward(erx):
+    log("NaN input")
+    sc = datagen.make_scene(22, 0, 20, 64, 12)
+    X, _ = datagen.lines(sc, 0, 12)
+    X[5, 3, 7] = float("nan")
+    got, _ = run_gpu(erx, X, scan_lines=4)
+    assert np.isfinite(got[:5]).all() and np.isnan(got[5:]).all()
+
+
+def test_normalisation_and_labels(erx):
+    log("normalisation + labels")
+    sc = datagen.make_scene(23, 0, 50, 300, 40)
+    X, mask = datagen.lines(sc, 0, 40)
+    det = erx.Detector(50, 300, 0.1, normalise=True, warmup=10)
+    det.push(X.cuda())
+    dn = det.scores_normalised().astype(np.float64)
+    r = oracle.run(X.numpy(), 0.1, 1e-5, normalise=True)
+    d = r["delta"]
+    m, s = d.mean(1, keepdims=True), d.std(1, keepdims=True)
+    tol = 2 * TOL * (d + m) / s + TOL * np.abs(r["delta_n"])
+    assert np.all(np.abs(dn - r["delta_n"]) <= tol)
+    tau = 3.0
+    lab = det.labels(tau)
+    want = (r["delta_n"] >= tau)
+    want[:10] = False
+    undecided = np.abs(r["delta_n"] - tau) <= tol
+    assert np.array_equal(lab.astype(bool)[~undecided], want[~undecided])
+    assert not lab[:10].any()
+
+
+def test_long_scan_224_full_size_sampled(erx):
+    """Full 20000 x 1024 x 224 scan in the benchmark's launch configuration;
+    sampled lines checked against the oracle run over a 256-line history
+    window.  The window starts from that line's own statistics, so the
+    background differs from the full history by a weight (1-a)^256 < 2e-12."""
+    sc = datagen.config_scenes(2)[0]
+    T = sc.lines
+    log(f"long-scan-224 full size: generating {T} x {sc.pixels} x {sc.bands} on the GPU")
+    X, _ = datagen.lines(sc, 0, T, device="cuda")
+    det = erx.Detector(sc.bands, sc.pixels, sc.momentum, block_lines=4096)
+    det.push(X)
+    got = det.scores()
+    torch.cuda.synchronize()
+    W = 256
+    for t in (0, 63, 64, 4095, 4096, 11111, T - 1):
+        a = max(0, t - W)
+        win = X[a:t + 1].cpu().numpy()
+        want = oracle.run(win, sc.momentum, 1e-5)["delta"][-1]
+        err = rel_err(got[t].cpu().numpy(), want)
+        log(f"  line {t}: max err {err.max():.3e}")
+        assert err.max() <= TOL
+    st = det.stats()
+    log(f"  stats {st}")
+    del X
+    torch.cuda.empty_cache()
