@@ -112,23 +112,54 @@ __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile
 // ============================================================================
 // Gram: per line, mean and centred covariance (Sec. III-C, Eqs. (18)-(19)).
 //
-// One wave computes a 64x64 block ("macro tile", 4x4 tiles of 16 bands) of
-// the upper triangle of the band x band Gram matrix of one line.  Pixels are
-// the contraction index.  Data are shifted by s = the FP32 mean of the first
-// min(64, p) pixels of each band (identical in every wave), products are
-// accumulated on FP32 MFMA over 64-pixel chunks, chunk partials are summed
-// in FP64, and the exact identity
+// A workgroup of 4 waves computes one 64x64 block ("macro tile", 4x4 tiles of
+// 16 bands) of the upper triangle of the band x band Gram matrix of one line;
+// wave w owns tile row 4*MI+w.  Pixels are the contraction index.  Chunks of
+// GCH pixels of the 64 row bands and 64 column bands are loaded with 16-byte
+// coalesced loads (prefetched one chunk ahead in registers) into LDS, from
+// which each lane reads its MFMA operands (one pixel, one band per lane).
+// Data are shifted by s = the FP32 mean of the first min(64, p) pixels of each
+// band (the same value in every workgroup), products are accumulated on FP32
+// MFMA over 64-pixel chunks and the chunk partials are summed in FP64; the
+// exact identity
 //     sum (x-mu)(x-mu)^T = sum (x-s)(x-s)^T - p (mu-s)(mu-s)^T
 // turns the shifted sums into the centred covariance.
 //
-// Grid: 8 * ceil(n/8) * nmacro one-wave blocks; block ids are spread so that
-// all macro tiles of one line run on the same XCD (consecutive block ids are
+// Grid: 8 * ceil(n/8) * nmacro workgroups; block ids are spread so that all
+// macro tiles of one line run on the same XCD (consecutive block ids are
 // dispatched round-robin over the 8 XCDs) and share its L2.
 // ============================================================================
+constexpr int GCH = 32;  // pixels per LDS chunk
+constexpr int GRS = 80;  // LDS row stride (floats): 64 bands + pad, conflict-free operand reads
+
 template <int DT>
-__global__ __launch_bounds__(64) void k_gram(const void* __restrict__ X, int n, int p, int b,
-                                             int NT, int nmacro, double* __restrict__ stats,
-                                             long long E)
+__device__ __forceinline__ f4 ld4_any(const void* X, size_t row, int band0, int b, bool vec_ok)
+{
+    f4 v;
+    if (vec_ok && band0 + 4 <= b) {
+        const size_t i = row + band0;
+        if (DT == DT_F32) {
+            v = *(const f4*)((const float*)X + i);
+        } else if (DT == DT_F16) {
+            const uint2 u = *(const uint2*)((const __half*)X + i);
+            const float2 a = __half22float2(*(const __half2*)&u.x), c = __half22float2(*(const __half2*)&u.y);
+            v = f4{a.x, a.y, c.x, c.y};
+        } else {
+            const uint2 u = *(const uint2*)((const uint16_t*)X + i);
+            const float s = 1.0f / 65536.0f;
+            v = f4{(float)(u.x & 0xffffu) * s, (float)(u.x >> 16) * s, (float)(u.y & 0xffffu) * s,
+                   (float)(u.y >> 16) * s};
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (band0 + q < b) ? ld1<DT>(X, row + band0 + q) : 0.0f;
+    }
+    return v;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n, int p, int b, int NT,
+                                              int nmacro, double* __restrict__ stats, long long E)
 {
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
@@ -136,7 +167,7 @@ __global__ __launch_bounds__(64) void k_gram(const void* __restrict__ X, int n, 
     const int ll = kk / nmacro;
     int m = kk - ll * nmacro;
     const int line = ll * 8 + xcd;
-    if (line >= n) return;
+    if (line >= n) return;  // uniform for the workgroup
     const int MT = (NT + 3) >> 2;
     int MI = 0;
     while (m >= MT - MI) {
@@ -145,116 +176,149 @@ __global__ __launch_bounds__(64) void k_gram(const void* __restrict__ X, int n, 
     }
     const int MJ = MI + m;
     const bool dg = (MI == MJ);
-    const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int I = 4 * MI + w;   // this wave's tile row
+    const bool rowok = I < NT;
+    const int rb0 = 64 * MI, cb0 = 64 * MJ;  // first band of the row / column panels
+
+    __shared__ __attribute__((aligned(16))) float Rs[GCH * GRS];
+    __shared__ __attribute__((aligned(16))) float Cs[GCH * GRS];
+    __shared__ float shift_s[128];
+
     const size_t lbase = (size_t)line * p * b;
-
-    int brow[4], bcol[4];
-    bool trow[4], tcol[4];  // tile exists
+    const bool vec_ok = (b & 3) == 0;
+    // staging map: per panel GCH*64 floats = GCH*16 float4; thread tid handles
+    // float4 number q = tid + 256*r (r < GCH*16/256), pixel q>>4, bands 4*(q&15)..
+    constexpr int NQ = GCH * 16 / 256;
+    f4 pr[NQ], pc[NQ];
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        brow[q] = 16 * (4 * MI + q) + c;
-        bcol[q] = 16 * (4 * MJ + q) + c;
-        trow[q] = (4 * MI + q) < NT;
-        tcol[q] = (4 * MJ + q) < NT;
-    }
-
-    // shift: FP32 mean of the first min(64, p) pixels
-    const int p0 = p < 64 ? p : 64;
-    float srow[4], scol[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        float s = 0.f, t = 0.f;
-        for (int k = g; k < p0; k += 4) {
-            const size_t r = lbase + (size_t)k * b;
-            if (brow[q] < b) s += ld1<DT>(X, r + brow[q]);
-            if (!dg && bcol[q] < b) t += ld1<DT>(X, r + bcol[q]);
+        for (int r = 0; r < NQ; ++r) {
+            const int q = tid + 256 * r, px = k0 + (q >> 4), b4 = 4 * (q & 15);
+            const bool okp = px < p;
+            const size_t row = lbase + (size_t)(okp ? px : 0) * b;
+            pr[r] = okp ? ld4_any<DT>(X, row, rb0 + b4, b, vec_ok) : f4{0.f, 0.f, 0.f, 0.f};
+            if (!dg) pc[r] = okp ? ld4_any<DT>(X, row, cb0 + b4, b, vec_ok) : f4{0.f, 0.f, 0.f, 0.f};
         }
-        s += __shfl_xor(s, 16);
-        s += __shfl_xor(s, 32);
-        t += __shfl_xor(t, 16);
-        t += __shfl_xor(t, 32);
-        srow[q] = s / (float)p0;
-        scol[q] = dg ? srow[q] : t / (float)p0;
-    }
+    };
+    auto stage = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const int q = tid + 256 * r, px = q >> 4, b4 = 4 * (q & 15);
+            *(f4*)&Rs[px * GRS + b4] = pr[r];
+            if (!dg) *(f4*)&Cs[px * GRS + b4] = pc[r];
+        }
+    };
+    const float* Cp = dg ? Rs : Cs;
 
-    double S[4][4][4];
-    double sr[4], sc[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        sr[a] = 0.0;
-        sc[a] = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) S[a][q][i] = 0.0;
-    }
-
-    for (int k0 = 0; k0 < p; k0 += 64) {
-        f4 acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[a][q] = f4{0.f, 0.f, 0.f, 0.f};
-        const int kend = (p - k0) < 64 ? (p - k0) : 64;
-        for (int ks = 0; ks < kend; ks += 4) {
-            const int pix = k0 + ks + g;
-            const bool ok = (ks + g) < kend;
-            const size_t r = lbase + (size_t)pix * b;
-            float av[4], bv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                av[q] = (ok && brow[q] < b) ? ld1<DT>(X, r + brow[q]) - srow[q] : 0.f;
-                if (dg)
-                    bv[q] = av[q];
-                else
-                    bv[q] = (ok && bcol[q] < b) ? ld1<DT>(X, r + bcol[q]) - scol[q] : 0.f;
-                sr[q] += (double)av[q];
-                sc[q] += (double)bv[q];
+    fetch(0);
+    stage();
+    __syncthreads();
+    // shift: FP32 mean of the first min(64, p) pixels, summed in pixel order
+    const int p0 = p < 64 ? p : 64;
+    if (tid < 128) {
+        const int col = tid & 63;
+        const bool isrow = tid < 64;
+        const int band = (isrow ? rb0 : cb0) + col;
+        float sum = 0.f;
+        if (band < b) {
+            const float* src = (isrow || dg) ? Rs : Cs;
+            for (int k = 0; k < p0 && k < GCH; ++k) sum += src[k * GRS + col];
+            for (int k = GCH; k < p0; ++k) {  // pixels of the second chunk, read from memory
+                sum += ld1<DT>(X, lbase + (size_t)k * b + band);
             }
+        }
+        shift_s[tid] = (band < b) ? sum / (float)p0 : 0.f;
+    }
+    __syncthreads();
+    const float sA = shift_s[16 * w + c];
+    float sB[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+    for (int q = 0; q < 4; ++q) sB[q] = shift_s[(dg ? 0 : 64) + 16 * q + c];
+
+    bool tok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tok[q] = rowok && (4 * MJ + q) < NT && (!dg || q >= w);
+
+    double S[4][4];
+    double sa = 0.0, sb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S[q][i] = 0.0;
+    f4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    float fa = 0.f, fb[4] = {0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < p; k0 += GCH) {
+        if (k0 > 0) {
+            stage();
+            __syncthreads();
+        }
+        if (k0 + GCH < p) fetch(k0 + GCH);  // prefetch the next chunk into registers
+        const int kend = (p - k0) < GCH ? (p - k0) : GCH;
+        if (rowok) {
+            for (int ks = 0; ks < kend; ks += 4) {
+                const int px = ks + g;
+                const bool ok = px < kend;
+                const float av = ok ? Rs[px * GRS + 16 * w + c] - sA : 0.f;
+                float bv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bv[q] = ok ? Cp[px * GRS + 16 * q + c] - sB[q] : 0.f;
+                fa += av;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fb[q] += bv[q];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (trow[a] && tcol[q] && (!dg || a <= q)) acc[a][q] = mfma(av[a], bv[q], acc[a][q]);
+                    if (tok[q]) acc[q] = mfma(av, bv[q], acc[q]);
+            }
         }
+        // FP64 sums of the FP32 partials every 64 pixels and at the end
+        if (((k0 + GCH) & 63) == 0 || k0 + GCH >= p) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) S[a][q][i] += (double)acc[a][q][i];
+                for (int i = 0; i < 4; ++i) S[q][i] += (double)acc[q][i];
+                acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+                sb[q] += (double)fb[q];
+                fb[q] = 0.f;
+            }
+            sa += (double)fa;
+            fa = 0.f;
+        }
+        __syncthreads();  // LDS is rewritten by the next chunk
     }
+    if (!rowok) return;
 
+    sa += __shfl_xor(sa, 16);
+    sa += __shfl_xor(sa, 32);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        sr[q] += __shfl_xor(sr[q], 16);
-        sr[q] += __shfl_xor(sr[q], 32);
-        sc[q] += __shfl_xor(sc[q], 16);
-        sc[q] += __shfl_xor(sc[q], 32);
+        sb[q] += __shfl_xor(sb[q], 16);
+        sb[q] += __shfl_xor(sb[q], 32);
     }
     const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
     double* ls = stats + (size_t)line * E;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int q = 0; q < 4; ++q) {
+        if (!tok[q]) continue;
+        double o[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (!(trow[a] && tcol[q] && (!dg || a <= q))) continue;
-            double o[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double srho = __shfl(sr[a], 4 * g + i);  // sum of row band 16I+4g+i
-                o[i] = (S[a][q][i] - srho * sc[q] * inv_p) * inv_p1;
-            }
-            double* dst = ls + tile_u(4 * MI + a, 4 * MJ + q, NT) * 256 + lane * 4;
-            *(double2*)dst = double2{o[0], o[1]};
-            *(double2*)(dst + 2) = double2{o[2], o[3]};
+        for (int i = 0; i < 4; ++i) {
+            const double srho = __shfl(sa, 4 * g + i);  // sum of row band 16I+4g+i
+            o[i] = (S[q][i] - srho * sb[q] * inv_p) * inv_p1;
         }
+        double* dst = ls + tile_u(I, 4 * MJ + q, NT) * 256 + lane * 4;
+        *(double2*)dst = double2{o[0], o[1]};
+        *(double2*)(dst + 2) = double2{o[2], o[3]};
     }
     if (dg && g == 0) {
         const long long ntU = (long long)NT * (NT + 1) / 2;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (trow[q]) ls[ntU * 256 + brow[q]] = (brow[q] < b) ? (double)srow[q] + sr[q] * inv_p : 0.0;
+        const int band = 16 * I + c;
+        ls[ntU * 256 + band] = (band < b) ? (double)sA + sa * inv_p : 0.0;
     }
 }
 
@@ -886,7 +950,7 @@ hipError_t launch_gram(int dtype, const void* X, int n, int p, int b, int NT, do
 {
     const int nm = gram_macros(NT);
     const long long nblk = (long long)((n + 7) / 8) * 8 * nm;
-    dim3 grid((unsigned)nblk), block(64);
+    dim3 grid((unsigned)nblk), block(256);
     switch (dtype) {
     case DT_F32: hipLaunchKernelGGL(k_gram<DT_F32>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
     case DT_F16: hipLaunchKernelGGL(k_gram<DT_F16>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
