@@ -84,13 +84,15 @@ typedef struct erx_config {
     int normalise;   /* 1: also produce line-normalised scores (erx_scores_normalised) */
     int block_lines; /* lines per device pass (scratch is sized for it); default 2048 */
     int scan_lines;  /* lines per segment of the chunked moving-average scan; default 64 */
+    int cond_estimate; /* 1-norm condition estimate per line: -1 (default) only when it decides
+                          the FP64 re-factor (0 < threshold < inf), 0 never, 1 always */
 } erx_config;
 
 #define ERX_MAX_BANDS 304
 
 /* Fill *cfg with defaults: ridge 1e-5, warmup 0, F32 input, FP32 Gram,
  * threshold 0 (FP64 factorisation), no normalisation, block_lines 2048,
- * scan_lines 64. */
+ * scan_lines 64, cond_estimate -1. */
 ERX_API void erx_config_default(erx_config *cfg, int bands, int pixels, float momentum);
 
 /* Create a detector on the current HIP device.  Returns NULL on error

@@ -41,7 +41,8 @@ class Config(C.Structure):
     _fields_ = [("bands", C.c_int), ("pixels", C.c_int), ("momentum", C.c_float),
                 ("ridge", C.c_float), ("warmup", C.c_int), ("dtype", C.c_int),
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
-                ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int)]
+                ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
+                ("cond_estimate", C.c_int)]
 
 
 class KernelTime(C.Structure):
@@ -133,7 +134,7 @@ class Detector:
     def __init__(self, bands: int, pixels: int, momentum: float = 0.1, ridge: float = 1e-5,
                  dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
-                 scan_lines: int = 64, stream: Optional[int] = -1):
+                 scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
         stream, None = a stream owned by the handle."""
         lib = load()
@@ -147,6 +148,7 @@ class Detector:
         cfg.warmup = int(warmup)
         cfg.block_lines = int(block_lines)
         cfg.scan_lines = int(scan_lines)
+        cfg.cond_estimate = int(cond_estimate)
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
         self._lib = lib

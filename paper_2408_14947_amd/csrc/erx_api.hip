@@ -190,6 +190,7 @@ void erx_config_default(erx_config* cfg, int bands, int pixels, float momentum)
     cfg->normalise = 0;
     cfg->block_lines = 2048;
     cfg->scan_lines = 64;
+    cfg->cond_estimate = -1;
 }
 
 erx_ctx* erx_create_ex(const erx_config* cfg)
@@ -225,6 +226,10 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
     }
     if (!(c.fp64_cond_threshold >= 0.0)) {
         fail(ERX_EINVAL, "fp64_cond_threshold must be >= 0");
+        return nullptr;
+    }
+    if (c.cond_estimate < -1 || c.cond_estimate > 1) {
+        fail(ERX_EINVAL, "cond_estimate must be -1, 0 or 1");
         return nullptr;
     }
     if (c.block_lines < 1 || c.scan_lines < 1 || c.warmup < 0 || (c.normalise != 0 && c.normalise != 1)) {
@@ -298,7 +303,8 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         }
     }
     const double thr = c.fp64_cond_threshold;
-    const int want_cond = std::isinf(thr) ? 0 : 1;
+    const bool decides = thr > 0.0 && !std::isinf(thr);  // the estimate picks the FP64 lines
+    const int want_cond = c.cond_estimate == 1 || (c.cond_estimate == -1 && decides) ? 1 : 0;
     const bool fp64_pass = !std::isinf(thr);
     h->last_t0 = h->t;
     for (int c0 = 0; c0 < n; c0 += C) {
@@ -328,15 +334,15 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
             if (fp64_pass)
                 HIPCHK(timed(h, K_CHOL64, [&] {
                     return launch_chol(1, 0, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
-                                       c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, 1, h->ctr,
-                                       h->stream);
+                                       c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, want_cond,
+                                       h->ctr, h->stream);
                 }));
         } else {
             // every line factored in FP64
             HIPCHK(timed(h, K_CHOL64, [&] {
                 return launch_chol(1, 1, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
-                                   c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, 1, h->ctr,
-                                   h->stream);
+                                   c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, want_cond,
+                                   h->ctr, h->stream);
             }));
         }
         float* out = h->scores + (size_t)c0 * c.pixels;

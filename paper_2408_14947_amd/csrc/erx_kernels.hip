@@ -114,14 +114,16 @@ __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile
 //
 // A workgroup of 4 waves computes one 64x64 block ("macro tile", 4x4 tiles of
 // 16 bands) of the upper triangle of the band x band Gram matrix of one line;
-// wave w owns tile row 4*MI+w.  Pixels are the contraction index.  Chunks of
-// GCH pixels of the 64 row bands and 64 column bands are loaded with 16-byte
-// coalesced loads (prefetched one chunk ahead in registers) into LDS, from
-// which each lane reads its MFMA operands (one pixel, one band per lane).
+// wave w owns tile row 4*MI+w.  Pixels are the contraction index.
+//
 // Data are shifted by s = the FP32 mean of the first min(64, p) pixels of each
-// band (the same value in every workgroup), products are accumulated on FP32
-// MFMA over 64-pixel chunks and the chunk partials are summed in FP64; the
-// exact identity
+// band (the same value in every workgroup).  Chunks of GCH pixels of the 64
+// row bands and the 64 column bands are loaded with 16-byte loads (one chunk
+// ahead, in registers), shifted, and stored transposed in LDS (band-major,
+// pixels contiguous), so that one 16-byte LDS read gives a lane the operands
+// of four consecutive MFMA k-steps.  Products are accumulated on FP32 MFMA
+// over 64-pixel chunks and the chunk partials are summed in FP64; the exact
+// identity
 //     sum (x-mu)(x-mu)^T = sum (x-s)(x-s)^T - p (mu-s)(mu-s)^T
 // turns the shifted sums into the centred covariance.
 //
@@ -129,14 +131,20 @@ __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile
 // macro tiles of one line run on the same XCD (consecutive block ids are
 // dispatched round-robin over the 8 XCDs) and share its L2.
 // ============================================================================
-constexpr int GCH = 32;  // pixels per LDS chunk
-constexpr int GRS = 80;  // LDS row stride (floats): 64 bands + pad, conflict-free operand reads
+constexpr int GCH = 32;           // pixels per LDS chunk
+constexpr int GTS = GCH + 4;      // LDS stride of one band row (floats), 16-byte aligned
+constexpr int GSR = 16 * GCH / 256;  // float4 per thread per panel and chunk
+constexpr int GSG = 256 / GCH;       // band-group stride between a thread's float4
 
+// four consecutive bands of one pixel row; bands >= b read 0.  With
+// vec_ok (b % 4 == 0, band0 % 4 == 0) the four bands are all valid or all
+// invalid, so one predicated 16-byte (8-byte) load serves.
 template <int DT>
 __device__ __forceinline__ f4 ld4_any(const void* X, size_t row, int band0, int b, bool vec_ok)
 {
-    f4 v;
-    if (vec_ok && band0 + 4 <= b) {
+    f4 v = f4{0.f, 0.f, 0.f, 0.f};
+    if (vec_ok) {
+        if (band0 >= b) return v;
         const size_t i = row + band0;
         if (DT == DT_F32) {
             v = *(const f4*)((const float*)X + i);
@@ -155,6 +163,25 @@ __device__ __forceinline__ f4 ld4_any(const void* X, size_t row, int band0, int 
         for (int q = 0; q < 4; ++q) v[q] = (band0 + q < b) ? ld1<DT>(X, row + band0 + q) : 0.0f;
     }
     return v;
+}
+
+// MFMA products of one LDS chunk for NQ column tiles (unconditional, so the
+// accumulators stay in place): lane group g supplies pixels u+4g..u+4g+3 for
+// the four k-steps of each 16-pixel group.
+template <int NQ>
+__device__ __forceinline__ void gram_chunk(const float* Rt, const float* Cp, int w, int c, int g, int kend,
+                                           f4* acc)
+{
+    for (int u = 0; u < kend; u += 16) {
+        const f4 av = *(const f4*)&Rt[(16 * w + c) * GTS + u + 4 * g];
+        f4 bv[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) bv[q] = *(const f4*)&Cp[(16 * q + c) * GTS + u + 4 * g];
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] = mfma(av[st], bv[q][st], acc[q]);
+    }
 }
 
 template <int DT>
@@ -179,71 +206,73 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63, g = lane >> 4, c = lane & 15;
-    const int I = 4 * MI + w;   // this wave's tile row
+    const int I = 4 * MI + w;  // this wave's tile row
     const bool rowok = I < NT;
     const int rb0 = 64 * MI, cb0 = 64 * MJ;  // first band of the row / column panels
 
-    __shared__ __attribute__((aligned(16))) float Rs[GCH * GRS];
-    __shared__ __attribute__((aligned(16))) float Cs[GCH * GRS];
+    __shared__ __attribute__((aligned(16))) float Rt[64 * GTS];  // [band][pixel]
+    __shared__ __attribute__((aligned(16))) float Ct[64 * GTS];
     __shared__ float shift_s[128];
+    __shared__ double bsum_s[128];
 
     const size_t lbase = (size_t)line * p * b;
     const bool vec_ok = (b & 3) == 0;
-    // staging map: per panel GCH*64 floats = GCH*16 float4; thread tid handles
-    // float4 number q = tid + 256*r (r < GCH*16/256), pixel q>>4, bands 4*(q&15)..
-    constexpr int NQ = GCH * 16 / 256;
-    f4 pr[NQ], pc[NQ];
+    // staging map: a panel chunk is GCH pixels x 16 groups of 4 bands; thread
+    // tid handles pixel tid % GCH of band groups tid / GCH + GSG * r, so that
+    // consecutive lanes write consecutive LDS words
+    const int spx = tid % GCH, sg0 = tid / GCH;
+    f4 pr[GSR], pc[GSR];
     auto fetch = [&](int k0) __attribute__((always_inline)) {
+        const int px = k0 + spx;
+        const bool okp = px < p;
+        const size_t row = lbase + (size_t)(okp ? px : 0) * b;
 #pragma unroll
-        for (int r = 0; r < NQ; ++r) {
-            const int q = tid + 256 * r, px = k0 + (q >> 4), b4 = 4 * (q & 15);
-            const bool okp = px < p;
-            const size_t row = lbase + (size_t)(okp ? px : 0) * b;
+        for (int r = 0; r < GSR; ++r) {
+            const int b4 = 4 * (sg0 + GSG * r);
             pr[r] = okp ? ld4_any<DT>(X, row, rb0 + b4, b, vec_ok) : f4{0.f, 0.f, 0.f, 0.f};
             if (!dg) pc[r] = okp ? ld4_any<DT>(X, row, cb0 + b4, b, vec_ok) : f4{0.f, 0.f, 0.f, 0.f};
         }
     };
-    auto stage = [&]() __attribute__((always_inline)) {
-#pragma unroll
-        for (int r = 0; r < NQ; ++r) {
-            const int q = tid + 256 * r, px = q >> 4, b4 = 4 * (q & 15);
-            *(f4*)&Rs[px * GRS + b4] = pr[r];
-            if (!dg) *(f4*)&Cs[px * GRS + b4] = pc[r];
-        }
-    };
-    const float* Cp = dg ? Rs : Cs;
 
-    fetch(0);
-    stage();
-    __syncthreads();
-    // shift: FP32 mean of the first min(64, p) pixels, summed in pixel order
+    // shift from the first min(64, p) pixels, summed in pixel order
     const int p0 = p < 64 ? p : 64;
     if (tid < 128) {
         const int col = tid & 63;
-        const bool isrow = tid < 64;
-        const int band = (isrow ? rb0 : cb0) + col;
+        const int band = (tid < 64 ? rb0 : cb0) + col;
         float sum = 0.f;
-        if (band < b) {
-            const float* src = (isrow || dg) ? Rs : Cs;
-            for (int k = 0; k < p0 && k < GCH; ++k) sum += src[k * GRS + col];
-            for (int k = GCH; k < p0; ++k) {  // pixels of the second chunk, read from memory
-                sum += ld1<DT>(X, lbase + (size_t)k * b + band);
-            }
-        }
+        if (band < b)
+            for (int k = 0; k < p0; ++k) sum += ld1<DT>(X, lbase + (size_t)k * b + band);
         shift_s[tid] = (band < b) ? sum / (float)p0 : 0.f;
     }
+    fetch(0);
     __syncthreads();
-    const float sA = shift_s[16 * w + c];
-    float sB[4];
+    auto stage = [&](int k0) __attribute__((always_inline)) {
+        const bool okp = k0 + spx < p;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sB[q] = shift_s[(dg ? 0 : 64) + 16 * q + c];
+        for (int r = 0; r < GSR; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int band = 4 * (sg0 + GSG * r) + j;
+                Rt[band * GTS + spx] = okp ? pr[r][j] - shift_s[band] : 0.f;
+                if (!dg) Ct[band * GTS + spx] = okp ? pc[r][j] - shift_s[64 + band] : 0.f;
+            }
+    };
+    // band sums of the shifted values: thread tid sums band (tid & 63) of panel
+    // (tid >> 6) & 1 over half (tid >> 7) of each chunk, straight from LDS
+    const int sband = tid & 63, spanel = (tid >> 6) & 1, shalf = tid >> 7;
+    const float* sumsrc = (spanel && !dg) ? Ct : Rt;
+    double bpart = 0.0;
+    const float* Cp = dg ? Rt : Ct;
 
-    bool tok[4];
+    // column tiles of this macro (the lower tiles of a diagonal macro are
+    // computed with the others and simply not stored)
+    const int nq = __builtin_amdgcn_readfirstlane((NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4);
+    int tbits = 0;  // column tiles this wave stores (wave-uniform)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) tok[q] = rowok && (4 * MJ + q) < NT && (!dg || q >= w);
+    for (int q = 0; q < 4; ++q) tbits |= (rowok && (4 * MJ + q) < NT && (!dg || q >= w)) ? (1 << q) : 0;
+    tbits = __builtin_amdgcn_readfirstlane(tbits);
 
     double S[4][4];
-    double sa = 0.0, sb[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -251,29 +280,28 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
     f4 acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-    float fa = 0.f, fb[4] = {0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < p; k0 += GCH) {
-        if (k0 > 0) {
-            stage();
-            __syncthreads();
-        }
+        stage(k0);
+        __syncthreads();
         if (k0 + GCH < p) fetch(k0 + GCH);  // prefetch the next chunk into registers
-        const int kend = (p - k0) < GCH ? (p - k0) : GCH;
+        {
+            const float* rowp = sumsrc + sband * GTS + (GCH / 2) * shalf;
+            float ps = 0.f;
+#pragma unroll
+            for (int q = 0; q < GCH / 8; ++q) {
+                const f4 v = *(const f4*)(rowp + 4 * q);
+                ps += (v[0] + v[1]) + (v[2] + v[3]);
+            }
+            bpart += (double)ps;
+        }
         if (rowok) {
-            for (int ks = 0; ks < kend; ks += 4) {
-                const int px = ks + g;
-                const bool ok = px < kend;
-                const float av = ok ? Rs[px * GRS + 16 * w + c] - sA : 0.f;
-                float bv[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) bv[q] = ok ? Cp[px * GRS + 16 * q + c] - sB[q] : 0.f;
-                fa += av;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) fb[q] += bv[q];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (tok[q]) acc[q] = mfma(av, bv[q], acc[q]);
+            const int kend = (p - k0) < GCH ? (p - k0) : GCH;
+            switch (nq) {
+            case 1: gram_chunk<1>(Rt, Cp, w, c, g, kend, acc); break;
+            case 2: gram_chunk<2>(Rt, Cp, w, c, g, kend, acc); break;
+            case 3: gram_chunk<3>(Rt, Cp, w, c, g, kend, acc); break;
+            default: gram_chunk<4>(Rt, Cp, w, c, g, kend, acc); break;
             }
         }
         // FP64 sums of the FP32 partials every 64 pixels and at the end
@@ -283,33 +311,29 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
 #pragma unroll
                 for (int i = 0; i < 4; ++i) S[q][i] += (double)acc[q][i];
                 acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-                sb[q] += (double)fb[q];
-                fb[q] = 0.f;
             }
-            sa += (double)fa;
-            fa = 0.f;
         }
         __syncthreads();  // LDS is rewritten by the next chunk
     }
+
+    // band sums: add the two halves
+    if (shalf == 1) bsum_s[spanel * 64 + sband] = bpart;
+    __syncthreads();
+    if (shalf == 0) bsum_s[spanel * 64 + sband] += bpart;
+    __syncthreads();
     if (!rowok) return;
 
-    sa += __shfl_xor(sa, 16);
-    sa += __shfl_xor(sa, 32);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        sb[q] += __shfl_xor(sb[q], 16);
-        sb[q] += __shfl_xor(sb[q], 32);
-    }
     const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
     double* ls = stats + (size_t)line * E;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (!tok[q]) continue;
+        if (!(tbits & (1 << q))) continue;
+        const double scol = bsum_s[(dg ? 0 : 64) + 16 * q + c];
         double o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double srho = __shfl(sa, 4 * g + i);  // sum of row band 16I+4g+i
-            o[i] = (S[q][i] - srho * sb[q] * inv_p) * inv_p1;
+            const double srho = bsum_s[16 * w + 4 * g + i];  // sum of row band 16I+4g+i
+            o[i] = (S[q][i] - srho * scol * inv_p) * inv_p1;
         }
         double* dst = ls + tile_u(I, 4 * MJ + q, NT) * 256 + lane * 4;
         *(double2*)dst = double2{o[0], o[1]};
@@ -318,7 +342,7 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
     if (dg && g == 0) {
         const long long ntU = (long long)NT * (NT + 1) / 2;
         const int band = 16 * I + c;
-        ls[ntU * 256 + band] = (band < b) ? (double)sA + sa * inv_p : 0.0;
+        ls[ntU * 256 + band] = (band < b) ? (double)shift_s[16 * w + c] + bsum_s[16 * w + c] * inv_p : 0.0;
     }
 }
 
@@ -420,6 +444,71 @@ __device__ __forceinline__ double bcast(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/sqrt(x): the hardware estimate, refined by Newton steps (two for FP64,
+// giving close to full double precision; one for FP32).
+__device__ __forceinline__ float rsqrt_nr(float x)
+{
+    float y = __builtin_amdgcn_rsqf(x);
+    return y * (1.5f - 0.5f * x * y * y);
+}
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
+// Cholesky and inverse of one 16x16 diagonal block by a single wave.
+// diag_s holds the block (row-major, stride 17) on entry; xt_s receives
+// X = L^{-1} (row-major, stride 17).  Rows of L live in lanes 0..15 and are
+// shared with lane broadcasts; the reciprocal pivots are wave-uniform and are
+// reused by the inverse, whose columns are computed by lanes 0..15 from the
+// broadcast rows of L.  Returns 1 if a pivot was not positive.
+template <class T>
+__device__ __forceinline__ int factor_diag16(T* diag_s, T* xt_s, int lane)
+{
+    const int r = lane & 15;
+    int bad = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T a[16], invd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = (q <= r) ? diag_s[r * 17 + q] : (T)0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const T akk = bcast(a[k], k);
+        if (!(akk > (T)0) && !(akk != akk)) bad = 1;  // a NaN pivot propagates, it is not "not PD"
+        const T inv = rsqrt_nr(akk);
+        invd[k] = inv;
+        const T lrk = (r > k) ? a[k] * inv : ((r == k) ? akk * inv : (T)0);
+        a[k] = lrk;
+#pragma unroll
+        for (int q = k + 1; q < 16; ++q) {
+            const T lqk = bcast(lrk, q);
+            if (r >= q) a[q] -= lrk * lqk;
+        }
+    }
+    // X = L^{-1}: lane c (= r) computes column c by forward substitution
+    T x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        T s0 = (q == r) ? (T)1 : (T)0, s1 = (T)0;
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            const T lqk = bcast(a[k], q);
+            if (k & 1) s1 -= lqk * x[k];
+            else s0 -= lqk * x[k];
+        }
+        x[q] = (s0 + s1) * invd[q];
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xt_s[q * 17 + lane] = x[q];  // xt[row][col] = X[row][col]
+    return bad;
+}
+
 template <int NT> struct CholLds {
     float part[NT * (NT + 1) / 2 * 32];  // per-tile partial sums (norms, mat-vecs)
     float vec[4][16 * NT];                // x, y, z, scratch vectors
@@ -468,10 +557,9 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
     for (int j = 0; j < SLOTS; ++j) {
         const int s = j * NW + w;
         int I = -1, J = -1;
-        if (s < NTL) {
-            I = (int)((__fsqrt_rn(8.0f * s + 1.0f) - 1.0f) * 0.5f);
+        if (s < NTL) {  // scalar decode of the lower-triangle tile index
+            I = 0;
             while ((I + 1) * (I + 2) / 2 <= s) ++I;
-            while (I * (I + 1) / 2 > s) --I;
             J = s - I * (I + 1) / 2;
         }
         tI[j] = I;
@@ -492,6 +580,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
 #pragma unroll
             for (int i = 0; i < 4; ++i) A[j][i] = (T)0;
         }
+        __builtin_amdgcn_sched_barrier(0);  // bound the number of loads in flight (registers)
     }
     if (!FB || force) {
         const long long ntU = NTL;
@@ -547,51 +636,23 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
         __syncthreads();
     }
 
-    // ---- blocked factorisation and inversion
-    for (int K = 0; K < NT; ++K) {
-        // 1a. owner of the diagonal tile publishes A_KK (slot holds A_KK^T)
+    // ---- blocked factorisation and inversion, with a one-step lookahead: the
+    //      wave that owns diagonal tile K+1 updates and factors it while the
+    //      other waves apply the rest of step K's trailing update
+    {
+        bool own = false;
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j)
-            if (tI[j] == K && tJ[j] == K)
+            if (tI[j] == 0 && tJ[j] == 0) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) diag_s[c * 17 + rowof<T>(g, i)] = A[j][i];
-        __syncthreads();
-        // 1b. one wave: L_KK (lanes = rows) and X = L_KK^{-1} (lanes = columns)
-        if (w == 0) {
-            const int r = lane & 15;
-            T a[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) a[q] = (q <= r) ? diag_s[r * 17 + q] : (T)0;
-            int bad = 0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const T akk = bcast(a[k], k);
-                if (akk <= (T)0) bad = 1;
-                const T dk = sqrt(akk);
-                const T inv = (T)1 / dk;
-                const T lrk = (r > k) ? a[k] * inv : ((r == k) ? dk : (T)0);
-                a[k] = lrk;
-#pragma unroll
-                for (int q = k + 1; q < 16; ++q) {
-                    const T lqk = bcast(lrk, q);
-                    if (r >= q) a[q] -= lrk * lqk;
-                }
+                own = true;
             }
-            T x[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                T s = (q == r) ? (T)1 : (T)0;
-#pragma unroll
-                for (int k = 0; k < q; ++k) s -= bcast(a[k], q) * x[k];
-                x[q] = s / bcast(a[q], q);
-            }
-            if (lane < 16)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) xt_s[q * 17 + lane] = x[q];  // xt[row][col] = X[row][col]
-            if (bad && lane == 0) fail_s = 1;
-        }
-        __syncthreads();
-        // 2. panel and inverse row
+        if (own && factor_diag16(diag_s, xt_s, lane) && lane == 0) fail_s = 1;
+    }
+    __syncthreads();
+    for (int K = 0; K < NT; ++K) {
+        // 2. panel L_IK^T = X A_IK^T and inverse row M_KJ = X T_KJ, X = L_KK^{-1}
         V xinvT;  // X^T in accumulator layout: element (row, c) = X[c][row]
 #pragma unroll
         for (int i = 0; i < 4; ++i) xinvT[i] = xt_s[c * 17 + rowof<T>(g, i)];
@@ -599,11 +660,11 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
         for (int j = 0; j < SLOTS; ++j) {
             if (tJ[j] == K && tI[j] > K) {
                 V z = {};
-                A[j] = mma_xty(z, xinvT, A[j]);  // L_IK^T = X A_IK^T
+                A[j] = mma_xty(z, xinvT, A[j]);
                 *(V*)&panel_s[tI[j] * 256 + lane * 4] = A[j];
             } else if (tI[j] == K && tJ[j] < K) {
                 V z = {};
-                A[j] = mma_xty(z, xinvT, A[j]);  // M_KJ = X T_KJ
+                A[j] = mma_xty(z, xinvT, A[j]);
                 *(V*)&mrow_s[tJ[j] * 256 + lane * 4] = A[j];
             } else if (tI[j] == K && tJ[j] == K) {
 #pragma unroll
@@ -612,11 +673,28 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
             }
         }
         __syncthreads();
-        // 3. trailing update of A and update of the inverse accumulators
+        // 3a. lookahead: diagonal tile K+1 is updated and factored first
+        {
+            bool own = false;
+#pragma unroll
+            for (int j = 0; j < SLOTS; ++j) {
+                if (tI[j] == K + 1 && tJ[j] == K + 1) {
+                    V xp = *(const V*)&panel_s[(K + 1) * 256 + lane * 4];
+                    const V yp = xp;
+                    xp = -xp;
+                    A[j] = mma_xty(A[j], xp, yp);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) diag_s[c * 17 + rowof<T>(g, i)] = A[j][i];
+                    own = true;
+                }
+            }
+            if (own && factor_diag16(diag_s, xt_s, lane) && lane == 0) fail_s = 1;
+        }
+        // 3b. the rest of the trailing update and the inverse accumulators
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
             const int I = tI[j], J = tJ[j];
-            if (I <= K) continue;
+            if (I <= K || (I == K + 1 && J == K + 1)) continue;
             if (J > K) {
                 V xp = *(const V*)&panel_s[J * 256 + lane * 4];
                 const V yp = *(const V*)&panel_s[I * 256 + lane * 4];

@@ -186,7 +186,7 @@ def test_forced_fp64_refactor(erx):
     log("threshold 0: every line re-factored in FP64")
     sc = datagen.make_scene(18, 0, 120, 400, 40)
     X, _ = datagen.lines(sc, 0, 40)
-    got, det = run_gpu(erx, X, fp64_cond_threshold=0.0, scan_lines=16)
+    got, det = run_gpu(erx, X, fp64_cond_threshold=0.0, scan_lines=16, cond_estimate=1)
     want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
     assert rel_err(got, want).max() <= TOL
     st = det.stats()
@@ -251,7 +251,7 @@ def test_condition_estimate_tracks_lapack(erx):
     log("condition estimate")
     sc = datagen.make_scene(20, 0, 64, 300, 20)
     X, _ = datagen.lines(sc, 0, 20)
-    _, det = run_gpu(erx, X, scan_lines=8)
+    _, det = run_gpu(erx, X, scan_lines=8, cond_estimate=1)
     cond, _ = det.line_info()
     r = oracle.run(X.numpy(), 0.1, 1e-5, history=True)
     for t in (0, 5, 19):

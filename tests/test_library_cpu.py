@@ -42,7 +42,8 @@ def test_library_exports_every_declared_symbol():
                                          ("momentum", 0.0), ("momentum", 1.5),
                                          ("momentum", float("nan")), ("ridge", -1e-3),
                                          ("dtype", 7), ("block_lines", 0), ("scan_lines", 0),
-                                         ("warmup", -1), ("fp64_cond_threshold", -1.0)])
+                                         ("warmup", -1), ("fp64_cond_threshold", -1.0),
+                                         ("cond_estimate", 2)])
 def test_create_rejects_invalid_config(field, value):
     erx, lib = _lib()
     cfg = erx.Config()
