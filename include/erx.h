@@ -157,6 +157,35 @@ typedef struct erx_kernel_time {
 ERX_API int erx_profile_enable(erx_ctx *h, int on);
 ERX_API int erx_profile_read(erx_ctx *h, erx_kernel_time *out, int max);
 
+/* ------------------------------------------------------------------------
+ * Many independent streams.  Each stream is its own detector (Sec. III applied
+ * to that stream alone) with its own band count, pixel count and momentum;
+ * ridge, input dtype, precision options, scan segment and pass capacity come
+ * from `common` (its bands / pixels / momentum fields are ignored).  A push
+ * gives every stream zero or more new lines; the library processes them in
+ * device passes that mix lines of all streams with the same number of
+ * 16-band tiles (longest work first), and can replay passes of identical
+ * shape from captured HIP graphs.  Line buffers of a batch must be device
+ * memory.
+ * ------------------------------------------------------------------------ */
+typedef struct erx_batch erx_batch;
+ERX_API erx_batch *erx_batch_create(int nstreams, const int *bands, const int *pixels, const float *momentum,
+                                    const erx_config *common);
+/* Order the batch's work after / before the caller's hipStream_t (NULL is the default stream);
+ * the batch itself runs on a stream of its own so that its passes can be captured. */
+ERX_API int erx_batch_set_stream(erx_batch *bt, void *hip_stream);
+/* lines[s]: device buffer [nlines[s]][pixels[s]][bands[s]] (ignored when nlines[s] == 0) */
+ERX_API int erx_batch_push(erx_batch *bt, const void *const *lines, const int *nlines);
+/* out[s]: buffer of nlines[s] * pixels[s] floats (host or device) receiving the scores of
+ * stream s's lines of the last push; blocks.  ERX_ENOTPD as for erx_scores. */
+ERX_API int erx_batch_scores(erx_batch *bt, float *const *out);
+ERX_API int erx_batch_get_state(erx_batch *bt, int stream, long long *t, double *mu, double *K);
+ERX_API int erx_batch_stats(erx_batch *bt, erx_stats_t *out);
+/* 1 (default): capture passes in HIP graphs and replay them; 0: launch every kernel */
+ERX_API int erx_batch_use_graphs(erx_batch *bt, int on);
+ERX_API int erx_batch_synchronize(erx_batch *bt);
+ERX_API void erx_batch_destroy(erx_batch *bt);
+
 /* Wait for all work enqueued on the handle's stream. */
 ERX_API int erx_synchronize(erx_ctx *h);
 

@@ -27,7 +27,9 @@ EXPORTS = (
     "erx_config_default", "erx_create", "erx_create_ex", "erx_set_stream", "erx_push_lines",
     "erx_push_lines_ex", "erx_scores", "erx_scores_device", "erx_scores_normalised", "erx_labels",
     "erx_get_state", "erx_set_state", "erx_stats", "erx_line_info", "erx_profile_enable",
-    "erx_profile_read", "erx_synchronize", "erx_destroy", "erx_last_error",
+    "erx_profile_read", "erx_batch_create", "erx_batch_set_stream", "erx_batch_push",
+    "erx_batch_scores", "erx_batch_get_state", "erx_batch_stats", "erx_batch_use_graphs",
+    "erx_batch_synchronize", "erx_batch_destroy", "erx_synchronize", "erx_destroy", "erx_last_error",
 )
 
 
@@ -83,6 +85,15 @@ def load(path: str = LIB_PATH):
         "erx_line_info": (ip, [vp, vp, vp]),
         "erx_profile_enable": (ip, [vp, ip]),
         "erx_profile_read": (ip, [vp, C.POINTER(KernelTime), ip]),
+        "erx_batch_create": (vp, [ip, vp, vp, vp, C.POINTER(Config)]),
+        "erx_batch_set_stream": (ip, [vp, vp]),
+        "erx_batch_push": (ip, [vp, vp, vp]),
+        "erx_batch_scores": (ip, [vp, vp]),
+        "erx_batch_get_state": (ip, [vp, ip, C.POINTER(C.c_longlong), vp, vp]),
+        "erx_batch_stats": (ip, [vp, C.POINTER(Stats)]),
+        "erx_batch_use_graphs": (ip, [vp, ip]),
+        "erx_batch_synchronize": (ip, [vp]),
+        "erx_batch_destroy": (None, [vp]),
         "erx_synchronize": (ip, [vp]),
         "erx_destroy": (None, [vp]),
         "erx_last_error": (C.c_char_p, []),
@@ -265,5 +276,101 @@ class Detector:
         return cond, flags
 
 
-__all__ = ["Detector", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
+class Batch:
+    """Many independent streams (one detector each) processed in shared device passes."""
+
+    def __init__(self, bands, pixels, momentum, ridge: float = 1e-5, dtype: str = "f32",
+                 fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
+                 scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True,
+                 stream: Optional[int] = -1):
+        lib = load()
+        self.bands = [int(x) for x in bands]
+        self.pixels = [int(x) for x in pixels]
+        ns = len(self.bands)
+        if len(self.pixels) != ns or len(momentum) != ns:
+            raise ValueError("bands, pixels and momentum need one entry per stream")
+        cfg = Config()
+        lib.erx_config_default(C.byref(cfg), 1, 2, 0.1)
+        cfg.ridge = float(ridge)
+        cfg.dtype = DTYPES[dtype]
+        cfg.fp64_cond_threshold = float(fp64_cond_threshold)
+        cfg.normalise = 1 if normalise else 0
+        cfg.block_lines = int(block_lines)
+        cfg.scan_lines = int(scan_lines)
+        cfg.cond_estimate = int(cond_estimate)
+        b = (C.c_int * ns)(*self.bands)
+        p = (C.c_int * ns)(*self.pixels)
+        m = (C.c_float * ns)(*[float(x) for x in momentum])
+        self._lib = lib
+        self._h = lib.erx_batch_create(ns, b, p, m, C.byref(cfg))
+        if not self._h:
+            raise ErxError(ERX_EINVAL, last_error())
+        self.nstreams = ns
+        self.dtype = dtype
+        self.last_n = [0] * ns
+        if stream == -1:
+            stream = _torch_stream()
+        if stream is not None:
+            _check(lib.erx_batch_set_stream(self._h, C.c_void_p(stream)))
+        _check(lib.erx_batch_use_graphs(self._h, 1 if graphs else 0))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.erx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, lines):
+        """lines[s]: device tensor [n_s, pixels_s, bands_s] or None (no lines)."""
+        ns = self.nstreams
+        ptrs = (C.c_void_p * ns)()
+        cnt = (C.c_int * ns)()
+        for s, x in enumerate(lines):
+            if x is None or x.shape[0] == 0:
+                ptrs[s], cnt[s] = None, 0
+                continue
+            if tuple(x.shape[1:]) != (self.pixels[s], self.bands[s]):
+                raise ValueError(f"stream {s}: lines must be [n, {self.pixels[s]}, {self.bands[s]}]")
+            ptrs[s], cnt[s] = _ptr(x), int(x.shape[0])
+        _check(self._lib.erx_batch_push(self._h, ptrs, cnt))
+        self.last_n = [int(cnt[s]) for s in range(ns)]
+
+    def scores(self, allow_notpd: bool = True):
+        """Scores of the last push: one float32 CUDA tensor [n_s, pixels_s] per stream (None if 0)."""
+        import torch
+        outs = [torch.empty((n, p), dtype=torch.float32, device="cuda") if n else None
+                for n, p in zip(self.last_n, self.pixels)]
+        arr = (C.c_void_p * self.nstreams)(*[(o.data_ptr() if o is not None else None) for o in outs])
+        torch.cuda.synchronize()
+        _check(self._lib.erx_batch_scores(self._h, arr), allow=(ERX_ENOTPD,) if allow_notpd else ())
+        return outs
+
+    def state(self, s: int):
+        t = C.c_longlong(0)
+        b = self.bands[s]
+        mu = np.empty(b)
+        K = np.empty((b, b))
+        _check(self._lib.erx_batch_get_state(self._h, int(s), C.byref(t), C.c_void_p(mu.ctypes.data),
+                                             C.c_void_p(K.ctypes.data)))
+        return int(t.value), mu, K
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(self._lib.erx_batch_stats(self._h, C.byref(st)))
+        return dict(lines=st.lines, fp64_refactors=st.fp64_refactors, notpd=st.notpd,
+                    max_cond=st.max_cond)
+
+    def use_graphs(self, on: bool):
+        _check(self._lib.erx_batch_use_graphs(self._h, 1 if on else 0))
+
+    def synchronize(self):
+        _check(self._lib.erx_batch_synchronize(self._h))
+
+
+__all__ = ["Detector", "Batch", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
            "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "MAX_BANDS"]

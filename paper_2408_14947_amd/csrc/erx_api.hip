@@ -13,24 +13,13 @@
 
 #include "../../include/erx.h"
 #include "erx_internal.h"
+#include "erx_runtime.h"
 
 using namespace erx;
 
 namespace {
 
-thread_local std::string g_err = "no error";
-
-int fail(int code, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
+#define fail erx::set_error
 #define HIPCHK(call)                                                                          \
     do {                                                                                      \
         hipError_t e_ = (call);                                                               \
@@ -68,43 +57,8 @@ struct erx_ctx {
     bool have_scores = false;
     // kernel timing
     bool profile = false;
-    std::vector<hipEvent_t> ev_pool;
-    struct Rec { int kernel; hipEvent_t a, b; };
-    std::vector<Rec> recs;
+    Profiler prof;
 };
-
-namespace {
-
-enum { K_GRAM, K_SCAN_LOCAL, K_SCAN_CARRY, K_CHOL32, K_CHOL64, K_SCORE, K_NORMALISE, K_COUNT };
-const char* kKernelNames[K_COUNT] = {"gram", "scan_local", "scan_carry", "chol_fp32", "chol_fp64",
-                                     "score", "normalise"};
-
-hipEvent_t take_event(erx_ctx* h)
-{
-    if (h->ev_pool.empty()) {
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    hipEvent_t e = h->ev_pool.back();
-    h->ev_pool.pop_back();
-    return e;
-}
-
-// run one launch, bracketed by events when profiling is on
-template <class F> hipError_t timed(erx_ctx* h, int kernel, F&& launch)
-{
-    if (!h->profile) return launch();
-    hipEvent_t a = take_event(h), b = take_event(h);
-    if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, h->stream);
-    if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(b, h->stream);
-    h->recs.push_back({kernel, a, b});
-    return e;
-}
-
-}  // namespace
 
 namespace {
 
@@ -114,11 +68,7 @@ void free_all(erx_ctx* h)
                     h->scores, h->scores_n, h->labels, h->staging};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    for (auto& r : h->recs) {
-        h->ev_pool.push_back(r.a);
-        h->ev_pool.push_back(r.b);
-    }
-    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    h->prof.release();
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
 }
 
@@ -173,7 +123,7 @@ long long packed_offset(int r, int c, int NT)
 
 extern "C" {
 
-const char* erx_last_error(void) { return g_err.c_str(); }
+const char* erx_last_error(void) { return erx::get_error(); }
 
 void erx_config_default(erx_config* cfg, int bands, int pixels, float momentum)
 {
@@ -317,40 +267,28 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
                                   hipMemcpyHostToDevice, h->stream));
             src = h->staging;
         }
-        const long long t0 = h->t;
-        HIPCHK(timed(h, K_GRAM, [&] { return launch_gram(c.dtype, src, nc, c.pixels, c.bands, h->NT, h->stats,
-                                                          h->E, h->stream); }));
-        HIPCHK(timed(h, K_SCAN_LOCAL, [&] { return launch_scan_local(h->stats, h->E, nc, seg, t0, c.momentum,
-                                                                      h->stream); }));
-        HIPCHK(timed(h, K_SCAN_CARRY, [&] { return launch_scan_carry(h->stats, h->carry, h->state, h->E, nc,
-                                                                      seg, t0, c.momentum, h->stream); }));
-        if (thr > 0.0) {
-            // FP32 factorisation; lines whose condition estimate exceeds thr are re-factored in FP64
-            HIPCHK(timed(h, K_CHOL32, [&] {
-                return launch_chol(0, 0, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
-                                   c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, want_cond, h->ctr,
-                                   h->stream);
-            }));
-            if (fp64_pass)
-                HIPCHK(timed(h, K_CHOL64, [&] {
-                    return launch_chol(1, 0, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
-                                       c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, want_cond,
-                                       h->ctr, h->stream);
-                }));
-        } else {
-            // every line factored in FP64
-            HIPCHK(timed(h, K_CHOL64, [&] {
-                return launch_chol(1, 1, h->NT, h->stats, h->carry, h->E, nc, seg, t0, c.momentum, c.ridge,
-                                   c.bands, h->Mt, h->mu32, h->flags + c0, h->cond + c0, thr, want_cond,
-                                   h->ctr, h->stream);
-            }));
-        }
-        float* out = h->scores + (size_t)c0 * c.pixels;
-        HIPCHK(timed(h, K_SCORE, [&] { return launch_score(c.dtype, h->NT, src, h->Mt, h->mu32, nc, c.pixels,
-                                                            c.bands, out, h->stream); }));
-        if (c.normalise)
-            HIPCHK(timed(h, K_NORMALISE, [&] { return launch_normalise(out, h->scores_n + (size_t)c0 * c.pixels,
-                                                                        nc, c.pixels, h->stream); }));
+        Pass P{};
+        P.sd = nullptr;
+        P.one.x = src;
+        P.one.out = h->scores + (size_t)c0 * c.pixels;
+        P.one.outn = c.normalise ? h->scores_n + (size_t)c0 * c.pixels : nullptr;
+        P.one.state = h->state;
+        P.one.t0 = h->t;
+        P.one.alpha = c.momentum;
+        P.one.eps = c.ridge;
+        P.one.p = c.pixels;
+        P.one.b = c.bands;
+        P.one.n = nc;
+        P.one.line0 = 0;
+        P.one.seg0 = 0;
+        P.nstreams = 1;
+        P.nlines = nc;
+        P.nseg = (nc + seg - 1) / seg;
+        P.seg = seg;
+        P.pmax = c.pixels;
+        HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
+                        h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
+                        h->profile ? &h->prof : nullptr));
         h->t += nc;
         if (!dev) HIPCHK(hipStreamSynchronize(h->stream));  // the staging buffer is reused
     }
@@ -492,26 +430,7 @@ int erx_profile_read(erx_ctx* h, erx_kernel_time* out, int max)
 {
     if (!h || (max > 0 && !out) || max < 0) return fail(ERX_EINVAL, "bad arguments");
     HIPCHK(hipStreamSynchronize(h->stream));
-    double ms[K_COUNT] = {0};
-    long long cnt[K_COUNT] = {0};
-    for (auto& r : h->recs) {
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
-        ms[r.kernel] += t;
-        cnt[r.kernel] += 1;
-        h->ev_pool.push_back(r.a);
-        h->ev_pool.push_back(r.b);
-    }
-    h->recs.clear();
-    int k = 0;
-    for (int i = 0; i < K_COUNT && k < max; ++i) {
-        if (!cnt[i]) continue;
-        std::snprintf(out[k].name, sizeof out[k].name, "%s", kKernelNames[i]);
-        out[k].launches = cnt[i];
-        out[k].total_ms = ms[i];
-        ++k;
-    }
-    return k;
+    return h->prof.read(out, max);
 }
 
 int erx_synchronize(erx_ctx* h)

@@ -15,19 +15,44 @@ constexpr int SCORE_PT = 2;  // 16-pixel tiles per wave in the score kernel
 // by the 16*NT mean entries.
 inline long long stat_entries(int NT) { return (long long)NT * (NT + 1) / 2 * 256 + 16LL * NT; }
 
-hipError_t launch_gram(int dtype, const void* X, int n, int p, int b, int NT, double* stats, long long E,
-                       hipStream_t s);
-hipError_t launch_scan_local(double* stats, long long E, int n, int seg, long long t0, double alpha,
-                             hipStream_t s);
-hipError_t launch_scan_carry(const double* stats, double* carry, double* state, long long E, int n, int seg,
-                             long long t0, double alpha, hipStream_t s);
-hipError_t launch_chol(int fp64, int force, int NT, const double* stats, const double* carry, long long E,
-                       int n, int seg, long long t0, double alpha, double eps, int b, float* Mt, float* mu32,
-                       int* flags, float* cond, double thr, int want_cond, unsigned long long* ctr,
-                       hipStream_t s);
-hipError_t launch_score(int dtype, int NT, const void* X, const float* Mt, const float* mu32, int n, int p,
-                        int b, float* out, hipStream_t s);
-hipError_t launch_normalise(const float* d, float* dn, int n, int p, hipStream_t s);
+// One stream's share of a device pass.  A pass processes lines of one or more
+// streams with the same number of 16-band tiles; its lines are numbered
+// 0..nlines-1 stream after stream (per-line scratch is indexed by that
+// number) and each stream's lines are cut into scan segments of `seg` lines,
+// numbered the same way.
+struct StreamDesc {
+    const void* x;    // first line of the stream in this pass (device memory)
+    float* out;       // scores of that line ([n][p])
+    float* outn;      // line-normalised scores, or null
+    double* state;    // moving-average carry of the stream (stat_entries entries)
+    long long t0;     // lines the stream had absorbed before this pass
+    double alpha;     // momentum
+    double eps;       // ridge
+    int p, b;         // pixels, bands
+    int n;            // lines of the stream in this pass
+    int line0;        // index of its first line in the pass
+    int seg0;         // index of its first scan segment in the pass
+    int pad_;
+};
+
+struct Pass {
+    const StreamDesc* sd;  // device table of nstreams entries, or null for one stream
+    StreamDesc one;        // the stream when sd is null
+    int nstreams;
+    int nlines;            // lines in the pass
+    int nseg;              // scan segments in the pass
+    int seg;               // lines per scan segment
+    int pmax;              // largest pixel count (sizes the score grid)
+};
+
+hipError_t launch_gram(int dtype, const Pass& P, int NT, double* stats, hipStream_t s);
+hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s);
+hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s);
+hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,
+                       float* Mt, float* mu32, int* flags, float* cond, double thr, int want_cond,
+                       unsigned long long* ctr, hipStream_t s);
+hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s);
+hipError_t launch_normalise(const Pass& P, hipStream_t s);
 hipError_t launch_labels(const float* dn, int n, int p, float tau, long long t0, int warmup,
                          unsigned char* out, hipStream_t s);
 

@@ -104,6 +104,37 @@ __device__ __forceinline__ f4 ld4(const void* X, size_t row, int band0, int b)
     return v;
 }
 
+template <int DT> __device__ __forceinline__ const void* advance(const void* x, size_t elems)
+{
+    return (const char*)x + elems * (DT == DT_F32 ? 4 : 2);
+}
+
+// the stream owning pass line `line` (streams are stored in line order)
+__device__ __forceinline__ StreamDesc stream_of_line(const Pass& P, int line)
+{
+    if (!P.sd) return P.one;
+    int lo = 0, hi = P.nstreams - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.sd[mid].line0 <= line) lo = mid;
+        else hi = mid - 1;
+    }
+    return P.sd[lo];
+}
+
+// the stream owning pass scan segment `g`
+__device__ __forceinline__ StreamDesc stream_of_seg(const Pass& P, int g)
+{
+    if (!P.sd) return P.one;
+    int lo = 0, hi = P.nstreams - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.sd[mid].seg0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return P.sd[lo];
+}
+
 __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile I <= J
 {
     return (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
@@ -185,8 +216,8 @@ __device__ __forceinline__ void gram_chunk(const float* Rt, const float* Cp, int
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n, int p, int b, int NT,
-                                              int nmacro, double* __restrict__ stats, long long E)
+__global__ __launch_bounds__(256) void k_gram(const Pass P, int NT, int nmacro, double* __restrict__ stats,
+                                              long long E)
 {
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
@@ -194,7 +225,10 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
     const int ll = kk / nmacro;
     int m = kk - ll * nmacro;
     const int line = ll * 8 + xcd;
-    if (line >= n) return;  // uniform for the workgroup
+    if (line >= P.nlines) return;  // uniform for the workgroup
+    const StreamDesc d = stream_of_line(P, line);
+    const int p = d.p, b = d.b;
+    const void* X = advance<DT>(d.x, (size_t)(line - d.line0) * p * b);
     const int MT = (NT + 3) >> 2;
     int MI = 0;
     while (m >= MT - MI) {
@@ -215,7 +249,7 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
     __shared__ float shift_s[128];
     __shared__ double bsum_s[128];
 
-    const size_t lbase = (size_t)line * p * b;
+    const size_t lbase = 0;
     const bool vec_ok = (b & 3) == 0;
     // staging map: a panel chunk is GCH pixels x 16 groups of 4 bands; thread
     // tid handles pixel tid % GCH of band groups tid / GCH + GSG * r, so that
@@ -355,14 +389,17 @@ __global__ __launch_bounds__(256) void k_gram(const void* __restrict__ X, int n,
 // segment; the Cholesky kernel adds D_l * carry, D_l = prod_{segment start..l}
 // (1-a_j), to obtain the full background of line l.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_scan_local(double* __restrict__ stats, long long E, int n,
-                                                    int seg, long long t0, double alpha)
+__global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __restrict__ stats, long long E)
 {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= E) return;
-    const int l0 = blockIdx.y * seg;
-    const int l1 = (l0 + seg) < n ? (l0 + seg) : n;
-    double* ptr = stats + e;
+    const int gsg = blockIdx.y;  // pass segment
+    const StreamDesc d = stream_of_seg(P, gsg);
+    const int l0 = (gsg - d.seg0) * P.seg;  // stream-local first line
+    const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
+    const double alpha = d.alpha;
+    const long long t0 = d.t0;
+    double* ptr = stats + (size_t)d.line0 * E + e;
     double acc = 0.0;
     int l = l0;
     for (; l + 8 <= l1; l += 8) {
@@ -392,22 +429,21 @@ __device__ __forceinline__ double seg_decay(long long t0, int l0, int l1, double
     return P;
 }
 
-__global__ __launch_bounds__(256) void k_scan_carry(const double* __restrict__ stats,
-                                                    double* __restrict__ carry,
-                                                    double* __restrict__ state, long long E, int n,
-                                                    int seg, long long t0, double alpha)
+__global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* __restrict__ stats,
+                                                    double* __restrict__ carry, long long E)
 {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= E) return;
-    double cv = state[e];
-    const int nseg = (n + seg - 1) / seg;
+    const StreamDesc d = P.sd ? P.sd[blockIdx.y] : P.one;
+    double cv = d.state[e];
+    const int nseg = (d.n + P.seg - 1) / P.seg;
     for (int gs = 0; gs < nseg; ++gs) {
-        carry[(size_t)gs * E + e] = cv;
-        const int l0 = gs * seg;
-        const int l1 = (l0 + seg) < n ? (l0 + seg) : n;
-        cv = seg_decay(t0, l0, l1, alpha) * cv + stats[(size_t)(l1 - 1) * E + e];
+        carry[(size_t)(d.seg0 + gs) * E + e] = cv;
+        const int l0 = gs * P.seg;
+        const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
+        cv = seg_decay(d.t0, l0, l1, d.alpha) * cv + stats[(size_t)(d.line0 + l1 - 1) * E + e];
     }
-    state[e] = cv;
+    d.state[e] = cv;
 }
 
 // ============================================================================
@@ -516,9 +552,8 @@ template <int NT> struct CholLds {
 };
 
 template <class T, int NT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ stats,
-                                                  const double* __restrict__ carry, long long E, int n,
-                                                  int seg, long long t0, double alpha, double eps, int b,
+__global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __restrict__ stats,
+                                                  const double* __restrict__ carry, long long E,
                                                   float* __restrict__ Mt, float* __restrict__ mu32,
                                                   int* __restrict__ flags, float* __restrict__ cond,
                                                   double threshold, int want_cond, int force,
@@ -530,7 +565,11 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
     constexpr bool FB = std::is_same<T, double>::value;
     constexpr int BP = 16 * NT;
     const int line = blockIdx.x;
-    if (line >= n) return;
+    if (line >= P.nlines) return;
+    const StreamDesc sdl = stream_of_line(P, line);
+    const int b = sdl.b, seg = P.seg;
+    const double eps = sdl.eps, alpha = sdl.alpha;
+    const long long t0 = sdl.t0;
     // the FP64 instantiation factors every line (force) or the lines the FP32 pass flagged
     if (FB && !force && !(flags[line] & FLAG_NEED_FP64)) return;  // uniform for the workgroup
 
@@ -543,9 +582,10 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
 
     const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63,
               g = lane >> 4, c = lane & 15;
-    const int gseg = line / seg, l0 = gseg * seg;
+    const int lloc = line - sdl.line0;  // stream-local line index
+    const int gseg = sdl.seg0 + lloc / seg, l0 = (lloc / seg) * seg;
     double D = 1.0;
-    for (int l = l0; l <= line; ++l) D *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
+    for (int l = l0; l <= lloc; ++l) D *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
     if (tid == 0) fail_s = 0;
 
     // ---- load A_IJ^T = (K_loc + D carry)_{JI} (+ eps on the diagonal)
@@ -906,20 +946,23 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const double* __restrict__ sta
 // Each wave scores PT tiles of 16 pixels; a workgroup is 4 waves.
 // ============================================================================
 template <int NT, int DT>
-__global__ __launch_bounds__(256) void k_score(const void* __restrict__ X, const float* __restrict__ Mt,
-                                               const float* __restrict__ mu32, int n, int p, int b,
-                                               int ngrp, float* __restrict__ out)
+__global__ __launch_bounds__(256) void k_score(const Pass P, const float* __restrict__ Mt,
+                                               const float* __restrict__ mu32, int ngrp)
 {
     constexpr int NTL = NT * (NT + 1) / 2;
     constexpr int PT = SCORE_PT;
     const int line = blockIdx.x / ngrp, grp = blockIdx.x - line * ngrp;
-    if (line >= n) return;
+    if (line >= P.nlines) return;
+    const StreamDesc d = stream_of_line(P, line);
+    const int p = d.p, b = d.b;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const int pix0 = (grp * 4 + w) * PT * 16;
     if (pix0 >= p) return;  // wave-uniform; the kernel has no barrier
+    const void* X = advance<DT>(d.x, (size_t)(line - d.line0) * p * b);
+    float* out = d.out + (size_t)(line - d.line0) * p;
     const float* mu = mu32 + (size_t)line * 16 * NT;
     const float* Ml = Mt + (size_t)line * NTL * 256 + lane * 4;
-    const size_t lrow = (size_t)line * p;
+    const size_t lrow = 0;
 
     f4 acc[NT][PT];
 #pragma unroll
@@ -967,13 +1010,15 @@ __global__ __launch_bounds__(256) void k_score(const void* __restrict__ X, const
 // Line normalisation (Sec. III-E, Eq. (24)): population mean and deviation of
 // the p scores of each line in FP64, (delta - mean) / std, 0 when std is 0.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ d, float* __restrict__ dn,
-                                                   int n, int p)
+__global__ __launch_bounds__(256) void k_normalise(const Pass P)
 {
     const int line = blockIdx.x;
-    if (line >= n) return;
+    if (line >= P.nlines) return;
+    const StreamDesc d = stream_of_line(P, line);
+    const int p = d.p;
     __shared__ double red[256];
-    const float* x = d + (size_t)line * p;
+    const float* x = d.out + (size_t)(line - d.line0) * p;
+    float* dn = d.outn + (size_t)(line - d.line0) * p;
     double s = 0.0;
     for (int i = threadIdx.x; i < p; i += 256) s += (double)x[i];
     red[threadIdx.x] = s;
@@ -997,8 +1042,7 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ d, 
     }
     const double sd = sqrt(red[0] / (double)p);
     for (int i = threadIdx.x; i < p; i += 256)
-        dn[(size_t)line * p + i] =
-            (sd > 0.0) ? (float)(((double)x[i] - mean) / sd) : (sd == 0.0 ? 0.0f : (float)sd);
+        dn[i] = (sd > 0.0) ? (float)(((double)x[i] - mean) / sd) : (sd == 0.0 ? 0.0f : (float)sd);
 }
 
 // ============================================================================
@@ -1023,34 +1067,33 @@ static int gram_macros(int NT)
     return MT * (MT + 1) / 2;
 }
 
-hipError_t launch_gram(int dtype, const void* X, int n, int p, int b, int NT, double* stats,
-                       long long E, hipStream_t s)
+hipError_t launch_gram(int dtype, const Pass& P, int NT, double* stats, hipStream_t s)
 {
     const int nm = gram_macros(NT);
-    const long long nblk = (long long)((n + 7) / 8) * 8 * nm;
+    const long long E = stat_entries(NT);
+    const long long nblk = (long long)((P.nlines + 7) / 8) * 8 * nm;
     dim3 grid((unsigned)nblk), block(256);
     switch (dtype) {
-    case DT_F32: hipLaunchKernelGGL(k_gram<DT_F32>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
-    case DT_F16: hipLaunchKernelGGL(k_gram<DT_F16>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
-    default: hipLaunchKernelGGL(k_gram<DT_U16>, grid, block, 0, s, X, n, p, b, NT, nm, stats, E); break;
+    case DT_F32: hipLaunchKernelGGL(k_gram<DT_F32>, grid, block, 0, s, P, NT, nm, stats, E); break;
+    case DT_F16: hipLaunchKernelGGL(k_gram<DT_F16>, grid, block, 0, s, P, NT, nm, stats, E); break;
+    default: hipLaunchKernelGGL(k_gram<DT_U16>, grid, block, 0, s, P, NT, nm, stats, E); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_scan_local(double* stats, long long E, int n, int seg, long long t0, double alpha,
-                             hipStream_t s)
+hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s)
 {
-    const int nseg = (n + seg - 1) / seg;
-    dim3 g1((unsigned)((E + 255) / 256), (unsigned)nseg);
-    hipLaunchKernelGGL(k_scan_local, g1, dim3(256), 0, s, stats, E, n, seg, t0, alpha);
+    const long long E = stat_entries(NT);
+    dim3 g1((unsigned)((E + 255) / 256), (unsigned)P.nseg);
+    hipLaunchKernelGGL(k_scan_local, g1, dim3(256), 0, s, P, stats, E);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_carry(const double* stats, double* carry, double* state, long long E, int n, int seg,
-                             long long t0, double alpha, hipStream_t s)
+hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s)
 {
-    dim3 g2((unsigned)((E + 255) / 256));
-    hipLaunchKernelGGL(k_scan_carry, g2, dim3(256), 0, s, stats, carry, state, E, n, seg, t0, alpha);
+    const long long E = stat_entries(NT);
+    dim3 g2((unsigned)((E + 255) / 256), (unsigned)P.nstreams);
+    hipLaunchKernelGGL(k_scan_carry, g2, dim3(256), 0, s, P, stats, carry, E);
     return hipGetLastError();
 }
 
@@ -1060,68 +1103,63 @@ template <class T, int NT> constexpr int chol_waves()
 }
 
 template <class T, int NT>
-static void chol_one(const double* stats, const double* carry, long long E, int n, int seg, long long t0,
-                     double alpha, double eps, int b, float* Mt, float* mu32, int* flags, float* cond,
-                     double thr, int want, int force, unsigned long long* ctr, hipStream_t s)
+static void chol_one(const Pass& P, const double* stats, const double* carry, float* Mt, float* mu32,
+                     int* flags, float* cond, double thr, int want, int force, unsigned long long* ctr,
+                     hipStream_t s)
 {
     constexpr int NW = chol_waves<T, NT>();
-    hipLaunchKernelGGL((k_chol<T, NT, NW>), dim3(n), dim3(NW * 64), 0, s, stats, carry, E, n, seg, t0,
-                       alpha, eps, b, Mt, mu32, flags, cond, thr, want, force, ctr);
+    const long long E = stat_entries(NT);
+    hipLaunchKernelGGL((k_chol<T, NT, NW>), dim3(P.nlines), dim3(NW * 64), 0, s, P, stats, carry, E, Mt, mu32,
+                       flags, cond, thr, want, force, ctr);
 }
 
 template <class T, int... NTs>
-static void chol_dispatch(std::integer_sequence<int, NTs...>, int NT, const double* stats,
-                          const double* carry, long long E, int n, int seg, long long t0, double alpha,
-                          double eps, int b, float* Mt, float* mu32, int* flags, float* cond,
-                          double thr, int want, int force, unsigned long long* ctr, hipStream_t s)
+static void chol_dispatch(std::integer_sequence<int, NTs...>, int NT, const Pass& P, const double* stats,
+                          const double* carry, float* Mt, float* mu32, int* flags, float* cond, double thr,
+                          int want, int force, unsigned long long* ctr, hipStream_t s)
 {
-    ((NT == NTs + 1 ? chol_one<T, NTs + 1>(stats, carry, E, n, seg, t0, alpha, eps, b, Mt, mu32, flags,
-                                           cond, thr, want, force, ctr, s)
+    ((NT == NTs + 1 ? chol_one<T, NTs + 1>(P, stats, carry, Mt, mu32, flags, cond, thr, want, force, ctr, s)
                     : void()),
      ...);
 }
 
-hipError_t launch_chol(int fp64, int force, int NT, const double* stats, const double* carry, long long E,
-                       int n, int seg, long long t0, double alpha, double eps, int b, float* Mt, float* mu32,
-                       int* flags, float* cond, double thr, int want_cond, unsigned long long* ctr,
-                       hipStream_t s)
+hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,
+                       float* Mt, float* mu32, int* flags, float* cond, double thr, int want_cond,
+                       unsigned long long* ctr, hipStream_t s)
 {
     if (NT < 1 || NT > MAX_NT) return hipErrorInvalidValue;
+    auto seq = std::make_integer_sequence<int, MAX_NT>();
     if (fp64)
-        chol_dispatch<double>(std::make_integer_sequence<int, MAX_NT>(), NT, stats, carry, E, n, seg, t0,
-                              alpha, eps, b, Mt, mu32, flags, cond, thr, want_cond, force, ctr, s);
+        chol_dispatch<double>(seq, NT, P, stats, carry, Mt, mu32, flags, cond, thr, want_cond, force, ctr, s);
     else
-        chol_dispatch<float>(std::make_integer_sequence<int, MAX_NT>(), NT, stats, carry, E, n, seg, t0,
-                             alpha, eps, b, Mt, mu32, flags, cond, thr, want_cond, 0, ctr, s);
+        chol_dispatch<float>(seq, NT, P, stats, carry, Mt, mu32, flags, cond, thr, want_cond, 0, ctr, s);
     return hipGetLastError();
 }
 
 template <int NT, int DT>
-static void score_one(const void* X, const float* Mt, const float* mu32, int n, int p, int b, float* out,
-                      hipStream_t s)
+static void score_one(const Pass& P, const float* Mt, const float* mu32, hipStream_t s)
 {
     const int per = 4 * SCORE_PT * 16;
-    const int ngrp = (p + per - 1) / per;
-    hipLaunchKernelGGL((k_score<NT, DT>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, X, Mt,
-                       mu32, n, p, b, ngrp, out);
+    const int ngrp = (P.pmax + per - 1) / per;
+    hipLaunchKernelGGL((k_score<NT, DT>), dim3((unsigned)((long long)P.nlines * ngrp)), dim3(256), 0, s, P, Mt,
+                       mu32, ngrp);
 }
 
 template <int DT, int... NTs>
-static void score_dispatch(std::integer_sequence<int, NTs...>, int NT, const void* X, const float* Mt,
-                           const float* mu32, int n, int p, int b, float* out, hipStream_t s)
+static void score_dispatch(std::integer_sequence<int, NTs...>, int NT, const Pass& P, const float* Mt,
+                           const float* mu32, hipStream_t s)
 {
-    ((NT == NTs + 1 ? score_one<NTs + 1, DT>(X, Mt, mu32, n, p, b, out, s) : void()), ...);
+    ((NT == NTs + 1 ? score_one<NTs + 1, DT>(P, Mt, mu32, s) : void()), ...);
 }
 
-hipError_t launch_score(int dtype, int NT, const void* X, const float* Mt, const float* mu32, int n, int p,
-                        int b, float* out, hipStream_t s)
+hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s)
 {
     if (NT < 1 || NT > MAX_NT) return hipErrorInvalidValue;
     auto seq = std::make_integer_sequence<int, MAX_NT>();
     switch (dtype) {
-    case DT_F32: score_dispatch<DT_F32>(seq, NT, X, Mt, mu32, n, p, b, out, s); break;
-    case DT_F16: score_dispatch<DT_F16>(seq, NT, X, Mt, mu32, n, p, b, out, s); break;
-    default: score_dispatch<DT_U16>(seq, NT, X, Mt, mu32, n, p, b, out, s); break;
+    case DT_F32: score_dispatch<DT_F32>(seq, NT, P, Mt, mu32, s); break;
+    case DT_F16: score_dispatch<DT_F16>(seq, NT, P, Mt, mu32, s); break;
+    default: score_dispatch<DT_U16>(seq, NT, P, Mt, mu32, s); break;
     }
     return hipGetLastError();
 }
@@ -1135,9 +1173,9 @@ hipError_t launch_labels(const float* dn, int n, int p, float tau, long long t0,
     return hipGetLastError();
 }
 
-hipError_t launch_normalise(const float* d, float* dn, int n, int p, hipStream_t s)
+hipError_t launch_normalise(const Pass& P, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_normalise, dim3(n), dim3(256), 0, s, d, dn, n, p);
+    hipLaunchKernelGGL(k_normalise, dim3(P.nlines), dim3(256), 0, s, P);
     return hipGetLastError();
 }
 

@@ -1,0 +1,146 @@
+"""Many uneven streams in shared device passes, against the FP64 oracle and
+against single-stream handles."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def log(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def erx():
+    import paper_2408_14947_amd as m
+    m.load()
+    return m
+
+
+def rel_err(got, want):
+    return np.abs(np.asarray(got, np.float64) - want) / np.maximum(np.abs(want), 1.0)
+
+
+def make_streams(specs, cfg=21):
+    scenes, data = [], []
+    for i, (b, p, T, a, kind, storage) in enumerate(specs):
+        sc = datagen.make_scene(cfg, i, b, p, T, kind=kind, storage=storage, momentum=a)
+        X, _ = datagen.lines(sc, 0, T)
+        scenes.append(sc)
+        data.append(X)
+    return scenes, data
+
+
+SPECS = [  # bands, pixels, lines, momentum, kind, storage
+    (37, 300, 70, 0.1, "mixture", "f32"),
+    (100, 130, 45, 0.3, "mixture", "f32"),
+    (48, 257, 90, 0.05, "mixture", "f32"),
+    (16, 640, 120, 0.2, "gauss", "f32"),
+    (5, 96, 33, 1.0, "gauss", "f32"),
+    (224, 300, 20, 0.1, "mixture", "f32"),
+    (40, 64, 150, 0.1, "mixture", "f32"),
+]
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_uneven_streams_match_oracle(erx, graphs):
+    log(f"uneven streams, graphs={graphs}")
+    scenes, data = make_streams(SPECS)
+    bt = erx.Batch([s[0] for s in SPECS], [s[1] for s in SPECS], [s[3] for s in SPECS],
+                   block_lines=96, scan_lines=16, graphs=graphs)
+    oras = [oracle.Stream(s[0], s[1], s[3], 1e-5) for s in SPECS]
+    dev = [X.cuda() for X in data]
+    # three pushes of uneven sizes per stream, some empty
+    cuts = [[0, 10, 10, 70], [0, 5, 30, 45], [0, 90, 90, 90], [0, 1, 60, 120], [0, 33, 33, 33],
+            [0, 7, 13, 20], [0, 64, 100, 150]]
+    for k in range(3):
+        chunk = [dev[s][cuts[s][k]:cuts[s][k + 1]] for s in range(len(SPECS))]
+        bt.push([x if x.shape[0] else None for x in chunk])
+        outs = bt.scores()
+        for s in range(len(SPECS)):
+            n = cuts[s][k + 1] - cuts[s][k]
+            if n == 0:
+                assert outs[s] is None
+                continue
+            want = oras[s].push(data[s][cuts[s][k]:cuts[s][k + 1]].numpy())["delta"]
+            err = rel_err(outs[s].cpu().numpy(), want).max()
+            assert err <= TOL, (k, s, err)
+    for s in range(len(SPECS)):
+        t, mu, K = bt.state(s)
+        assert t == SPECS[s][2]
+
+
+def test_batch_equals_single_stream_handles(erx):
+    log("batch vs single handles")
+    specs = SPECS[:4]
+    scenes, data = make_streams(specs)
+    bt = erx.Batch([s[0] for s in specs], [s[1] for s in specs], [s[3] for s in specs],
+                   block_lines=128, scan_lines=16)
+    bt.push([X.cuda() for X in data])
+    outs = bt.scores()
+    for s, (b, p, T, a, _, _) in enumerate(specs):
+        det = erx.Detector(b, p, a, block_lines=128, scan_lines=16)
+        det.push(data[s].cuda())
+        single = det.scores().cpu().numpy()
+        assert rel_err(outs[s].cpu().numpy(), single.astype(np.float64)).max() <= 1e-6
+
+
+def test_graph_replays_match_eager(erx):
+    """Passes of identical shape replay one captured graph; eager work and
+    synchronisations run between the replays, and every replay is checked."""
+    log("graph replay vs eager")
+    specs = [(12, 320, 128, 0.15, "gauss", "f32")] * 6
+    scenes, data = make_streams(specs, cfg=22)
+    dev = [X.cuda() for X in data]
+    g = erx.Batch([s[0] for s in specs], [s[1] for s in specs], [s[3] for s in specs],
+                  block_lines=96, scan_lines=16, graphs=True)
+    e = erx.Batch([s[0] for s in specs], [s[1] for s in specs], [s[3] for s in specs],
+                  block_lines=96, scan_lines=16, graphs=False)
+    for k in range(4):
+        part = [x[32 * k:32 * (k + 1)] for x in dev]
+        g.push(part)
+        og = g.scores()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        e.push(part)
+        oe = e.scores()
+        for a, b in zip(og, oe):
+            assert torch.equal(a, b), k
+        del junk
+
+
+def test_batch_multispectral_f16(erx):
+    """Small-band streams stored in FP16 (4..16 bands, per-stream momentum)."""
+    log("multispectral f16")
+    scs = datagen.config_scenes(4, scale_lines=60, streams=24)
+    data = [datagen.lines(sc, 0, sc.lines)[0] for sc in scs]
+    bt = erx.Batch([sc.bands for sc in scs], [sc.pixels for sc in scs], [sc.momentum for sc in scs],
+                   dtype="f16", block_lines=512, scan_lines=32)
+    bt.push([X.cuda() for X in data])
+    outs = bt.scores()
+    for sc, X, o in zip(scs, data, outs):
+        want = oracle.run(datagen.storage_to_float64(X, "f16"), sc.momentum, 1e-5)["delta"]
+        assert rel_err(o.cpu().numpy(), want).max() <= TOL
+
+
+def test_batch_uneven_u16(erx):
+    """Uneven band/pixel counts, uint16 counts scaled by 2^-16."""
+    log("uneven u16")
+    scs = datagen.config_scenes(3, scale_lines=24, streams=6)
+    data = [datagen.lines(sc, 0, sc.lines)[0] for sc in scs]
+    bt = erx.Batch([sc.bands for sc in scs], [sc.pixels for sc in scs], [sc.momentum for sc in scs],
+                   dtype="u16", block_lines=64, scan_lines=8)
+    bt.push([X.cuda() for X in data])
+    outs = bt.scores()
+    for sc, X, o in zip(scs, data, outs):
+        want = oracle.run(datagen.storage_to_float64(X, "u16"), sc.momentum, 1e-5)["delta"]
+        err = rel_err(o.cpu().numpy(), want).max()
+        log(f"  b={sc.bands} p={sc.pixels}: max err {err:.2e}")
+        assert err <= TOL
