@@ -8,9 +8,12 @@ and inverse factor, scoring.  Inputs are generated on the GPU and resident in
 HBM before the timed region.  Prints one JSON line.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -19,6 +22,109 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ERX pixels/s + lines/s at 108/224 bands; mixed/batched vs plain FP32 at stated err"
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+KERNEL_SRC = os.path.join(ROOT, "paper_2408_14947_amd", "csrc", "erx_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_long-scan-224.md")
+WORKLOAD = ("long-scan-224: one stream, 20000 lines x 1024 px x 224 bands, f32, momentum 0.1, "
+            "ridge 1e-5, drifting 4-endmember mixture, 0.2% 3x3 patches")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_kernel(name):
+    """Map a device kernel's demangled name to the short name the library's profiler uses."""
+    m = re.search(r"erx::k_(\w+?)(<([^>]*)>)?\(", name)
+    if not m:
+        return None
+    k = m.group(1)
+    if k == "chol":
+        return "chol_fp64" if (m.group(3) or "").startswith("double") else "chol_fp32"
+    return k
+
+
+def _csv_rows(d, suffix):
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def summarize_trace(d, command):
+    """Markdown table of rocprofv3's kernel statistics (--kernel-trace --stats -f csv)."""
+    rows = _csv_rows(d, "kernel_stats.csv")
+    if not rows:
+        sys.exit(f"no *kernel_stats.csv under {d}")
+    out = ["# Kernel trace: " + WORKLOAD, "", "Command (repository root on the GPU host):", "",
+           "```", command, "```", "",
+           f"Kernel source sha256[:16] = {kernel_source_hash()}", "",
+           "| kernel | calls | total_ms | avg_us | min_us | max_us | pct |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        nm = short_kernel(r["Name"]) or (r["Name"][:60] + ("..." if len(r["Name"]) > 60 else ""))
+        out.append(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def summarize_counters(dirs, command, copy_bytes, block_lines):
+    """HBM traffic per dispatch from one FETCH_SIZE and one WRITE_SIZE pass.
+
+    Each pass also ran a plain device copy of copy_bytes; the ratio of the known bytes to what
+    the counter reports for that copy scales the counter for the library's kernels."""
+    per = {}     # counter -> kernel -> [KiB per dispatch]
+    copy = {}    # counter -> KiB of the calibration copy
+    for d in dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            cn, v, nm = r["Counter_Name"], float(r["Counter_Value"]), r["Kernel_Name"]
+            k = short_kernel(nm)
+            if k:
+                per.setdefault(cn, {}).setdefault(k, []).append(v)
+            elif "neg_kernel" in nm:
+                copy[cn] = max(copy.get(cn, 0.0), v)
+    rec = {"source_sha256": kernel_source_hash(), "block_lines": block_lines,
+           "copy_bytes": copy_bytes, "scale": {}, "kernels": {}}
+    for cn in ("FETCH_SIZE", "WRITE_SIZE"):
+        if cn not in copy:
+            sys.exit(f"calibration copy not found for {cn}")
+        rec["scale"][cn] = copy_bytes / (copy[cn] * 1024.0)
+    for cn, ks in per.items():
+        for k, vals in ks.items():
+            kb = sum(vals) / len(vals)
+            e = rec["kernels"].setdefault(k, {"dispatches": len(vals)})
+            e[cn.lower() + "_kib"] = kb
+            e[cn.lower().replace("_size", "") + "_bytes"] = kb * 1024.0 * rec["scale"][cn]
+    for e in rec["kernels"].values():
+        e["bytes"] = e.get("fetch_bytes", 0.0) + e.get("write_bytes", 0.0)
+    out = ["# HBM traffic per dispatch: " + WORKLOAD, "", "Commands (repository root on the GPU host):",
+           "", "```", command, "```", "",
+           f"Calibration: a plain device copy of {copy_bytes} bytes reads FETCH_SIZE = "
+           f"{copy['FETCH_SIZE']:.0f} KiB and writes WRITE_SIZE = {copy['WRITE_SIZE']:.0f} KiB; "
+           f"scale factors {rec['scale']['FETCH_SIZE']:.4f} (fetch), {rec['scale']['WRITE_SIZE']:.4f} (write).",
+           "", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB read | scaled MB written |",
+           "|---|---|---|---|---|---|"]
+    for k, e in sorted(rec["kernels"].items(), key=lambda kv: -kv[1]["bytes"]):
+        out.append(f"| {k} | {e['dispatches']} | {e.get('fetch_size_kib', 0):.0f} | "
+                   f"{e.get('write_size_kib', 0):.0f} | {e.get('fetch_bytes', 0) / 1e6:.1f} | "
+                   f"{e.get('write_bytes', 0) / 1e6:.1f} |")
+    out += ["", "Machine-readable record (read by bench.py while the kernel source hash matches):", "",
+            "```json", json.dumps(rec), "```"]
+    return "\n".join(out)
+
+
+def load_traffic(kernel, block_lines):
+    """Scaled HBM bytes per launch of `kernel`, or None when the counters are stale or missing."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("block_lines") != block_lines:
+        return None
+    e = rec["kernels"].get(kernel)
+    return None if e is None else e["bytes"]
 
 
 def kernel_work(name, b, p):
@@ -74,10 +180,20 @@ def main():
                     help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-108", action="store_true", help="skip the 108-band side measurement")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run one device-to-device copy of BYTES bytes (calibrates the "
-                         "FETCH_SIZE / WRITE_SIZE counters against a known traffic) and exit")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device copy of BYTES bytes (a known traffic against "
+                         "which the FETCH_SIZE / WRITE_SIZE counters are scaled)")
+    ap.add_argument("--rocprof-summary", nargs="+", metavar="DIR",
+                    help="no GPU: print a markdown summary of rocprofv3 CSV output under DIR(s)")
+    ap.add_argument("--rocprof-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        if args.calibrate_copy:
+            print(summarize_counters(args.rocprof_summary, args.rocprof_command, args.calibrate_copy,
+                                     args.block_lines))
+        else:
+            print(summarize_trace(args.rocprof_summary[0], args.rocprof_command))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent streams and line blocks would shard across GPUs, see the design notes)",
@@ -87,15 +203,15 @@ def main():
     import numpy as np
     import torch
 
-    if args.copy_calibration:
-        n = args.copy_calibration // 4
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)  # one elementwise kernel: reads and writes n floats
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": 4 * n}))
-        return
+        del src, dst
+        torch.cuda.empty_cache()
 
     import datagen
     import paper_2408_14947_amd as erx
@@ -142,15 +258,15 @@ def main():
         kv["achieved"] = rate / (1e12 if un == "flop" else 1e9)
         kv["unit"] = "TFLOP/s" if un == "flop" else "GB/s"
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": runit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / peak, 4), "traffic": load_traffic(dom, args.block_lines),
+                "traffic_unit": "bytes/launch", "kernel": dom,
                 "work_per_launch": work_launch, "lines_per_launch": lines_per_launch}
 
     out = {
         "metric": METRIC, "value": pix_s, "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "long-scan-224: one stream, 20000 lines x 1024 px x 224 bands, f32, "
-                               "momentum 0.1, ridge 1e-5, drifting 4-endmember mixture, 0.2% 3x3 patches",
+        "config": {"workload": WORKLOAD,
                    "lines": T, "pixels": p, "bands": b, "block_lines": args.block_lines,
                    "fp64_cond_threshold": 0.0 if args.fp64_threshold is None else args.fp64_threshold},
         "lines_per_s": lines_s, "wall_s": wall, "roofline": roofline, "kernels": kernels,
