@@ -80,6 +80,20 @@ def test_parity_shapes(erx, b, p, T, blk, seg):
     assert err.max() <= TOL
 
 
+@pytest.mark.parametrize("nt", range(1, 20))
+def test_every_tile_count(erx, nt):
+    """Every 16-band tile count the kernels instantiate, up to the 304-band maximum."""
+    b = 304 if nt == 19 else 16 * nt - (nt % 3) * 5
+    p, T = 80 + nt, 14
+    log(f"tile count {nt}: b={b} p={p} T={T}")
+    sc = datagen.make_scene(31, nt, b, p, T, momentum=0.2)
+    X, _ = datagen.lines(sc, 0, T)
+    got, _ = run_gpu(erx, X, 0.2, block_lines=9, scan_lines=4)
+    want = oracle.run(X.numpy(), 0.2, 1e-5)["delta"]
+    err = rel_err(got, want).max()
+    assert err <= TOL, err
+
+
 def test_parity_plain_108_full(erx):
     """500 lines x 640 px x 108 bands (the single-stream 108-band workload)."""
     sc = datagen.config_scenes(1)[0]
