@@ -168,6 +168,53 @@ def time_workload(erx, torch, X, b, p, momentum, steps, warmup, block_lines, str
     return ms, wall, prof, st
 
 
+# frozen error bounds of the reduced-precision Gram (max, p99 of the relative score error)
+MIXED_BOUNDS = {"bf16": (1e-2, 3e-3), "fp16": (1e-3, 5e-4)}
+
+
+def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof):
+    """BF16 / FP16 Gram with FP32 Cholesky (FP64 re-factor above a condition estimate of 1e6)
+    on the same scan: throughput, and the score error against the plain FP32 GPU path over
+    every pixel of the scan (the plain path is itself within 1e-4 of the FP64 oracle)."""
+    T = X.shape[0]
+
+    def scores(**kw):
+        det = erx.Detector(b, p, momentum, block_lines=args.block_lines, stream=stream.cuda_stream, **kw)
+        det.push(X)
+        s = det.scores()
+        det.synchronize()
+        det.close()
+        return s
+
+    with torch.cuda.stream(stream):
+        ref = scores()
+    res = {"plain_ms_per_step": plain_ms, "plain_gram_ms": plain_prof["gram"][1] / plain_prof["gram"][0]}
+    for prec in ("bf16", "fp16"):
+        kw = dict(precision=prec, fp64_cond_threshold=1e6, cond_estimate=1)
+        ms, _, prof, st = time_workload(erx, torch, X, b, p, momentum, args.steps, args.warmup,
+                                        args.block_lines, stream, profile=True, **kw)
+        with torch.cuda.stream(stream):
+            got = scores(**kw)
+            e = ((got.double() - ref.double()).abs() / ref.double().abs().clamp_min(1.0)).flatten()
+            k = max(1, e.numel() // 100)
+            p99 = float(torch.topk(e, k).values.min())
+            emax, emed = float(e.max()), float(e.median())
+        torch.cuda.synchronize()
+        gram_ms = prof["gram"][1] / prof["gram"][0]
+        flops = kernel_work("gram", b, p)[1] * T * args.steps / prof["gram"][0]
+        res[prec] = {"ms_per_step": ms / args.steps, "pixels_per_s": T * p * args.steps / (ms / 1e3),
+                     "speedup_vs_plain": plain_ms / (ms / args.steps),
+                     "gram_ms": gram_ms, "gram_tflops": flops / (gram_ms / 1e3) / 1e12,
+                     "gram_peak_tflops": 2500.0,
+                     "err_vs_plain": {"max": emax, "p99": p99, "median": emed},
+                     "bound": {"max": MIXED_BOUNDS[prec][0], "p99": MIXED_BOUNDS[prec][1]},
+                     "fp64_refactors": st["fp64_refactors"], "max_cond": st["max_cond"],
+                     "kernels_ms": {k: v[1] / v[0] for k, v in prof.items()}}
+        del got, e
+    del ref
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +227,8 @@ def main():
                     help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-108", action="store_true", help="skip the 108-band side measurement")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the reduced-precision (BF16 / FP16 Gram) side measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known traffic against "
                          "which the FETCH_SIZE / WRITE_SIZE counters are scaled)")
@@ -272,6 +321,8 @@ def main():
         "lines_per_s": lines_s, "wall_s": wall, "roofline": roofline, "kernels": kernels,
         "fp64_refactors": st["fp64_refactors"], "max_cond": st["max_cond"],
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(erx, torch, X, b, p, sc.momentum, args, stream, ms_step, prof)
     del X
     torch.cuda.empty_cache()
 

@@ -280,6 +280,7 @@ class Batch:
     """Many independent streams (one detector each) processed in shared device passes."""
 
     def __init__(self, bands, pixels, momentum, ridge: float = 1e-5, dtype: str = "f32",
+                 precision: str = "fp32",
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
                  scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True,
                  stream: Optional[int] = -1):
@@ -293,6 +294,7 @@ class Batch:
         lib.erx_config_default(C.byref(cfg), 1, 2, 0.1)
         cfg.ridge = float(ridge)
         cfg.dtype = DTYPES[dtype]
+        cfg.precision = PRECISIONS[precision]
         cfg.fp64_cond_threshold = float(fp64_cond_threshold)
         cfg.normalise = 1 if normalise else 0
         cfg.block_lines = int(block_lines)

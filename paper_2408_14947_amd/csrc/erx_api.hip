@@ -170,8 +170,8 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "unknown dtype %d", c.dtype);
         return nullptr;
     }
-    if (c.precision != ERX_GRAM_FP32) {
-        fail(ERX_EINVAL, "precision %d is not available", c.precision);
+    if (c.precision != ERX_GRAM_FP32 && c.precision != ERX_GRAM_BF16 && c.precision != ERX_GRAM_FP16) {
+        fail(ERX_EINVAL, "unknown precision %d", c.precision);
         return nullptr;
     }
     if (!(c.fp64_cond_threshold >= 0.0)) {
@@ -286,7 +286,8 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.nseg = (nc + seg - 1) / seg;
         P.seg = seg;
         P.pmax = c.pixels;
-        HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
+        P.vec4 = (c.bands % 4) == 0;
+        HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, c.precision, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));
         h->t += nc;

@@ -53,7 +53,7 @@ struct Group {
     hipEvent_t slot_ev[NSLOT] = {nullptr, nullptr};
     int next_slot = 0;
     // graphs keyed by (slot, nstreams, nlines, nseg, pmax)
-    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;  // (slot, nsd, L, S, pmax, vec4)
 };
 
 size_t esize(int dtype) { return dtype == ERX_F32 ? 4 : 2; }
@@ -130,7 +130,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     }
     const erx_config& c = *common;
     if (!(c.ridge >= 0.0f) || !std::isfinite(c.ridge) || (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16) ||
-        c.precision != ERX_GRAM_FP32 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
+        c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_FP16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1)) {
         fail(ERX_EINVAL, "erx_batch_create: invalid common configuration");
         return nullptr;
@@ -283,7 +283,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
             g.next_slot = (g.next_slot + 1) % NSLOT;
             HIPCHK(hipEventSynchronize(g.slot_ev[slot]));  // the slot's previous upload has run
             StreamDesc* hd = g.h_sd[slot];
-            int L = 0, S = 0, nsd = 0, pmax = 0;
+            int L = 0, S = 0, nsd = 0, pmax = 0, vec4 = 1;
             std::vector<std::pair<int, int>> taken;  // (group index, lines)
             for (int k : act) {
                 const int s = g.streams[k];
@@ -308,6 +308,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
                 L += kl;
                 S += (kl + seg - 1) / seg;
                 pmax = std::max(pmax, B.p);
+                vec4 = vec4 && (B.b % 4 == 0);
                 taken.push_back({k, kl});
             }
             Pass P{};
@@ -317,15 +318,16 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
             P.nseg = S;
             P.seg = seg;
             P.pmax = pmax;
+            P.vec4 = vec4;
             auto record = [&]() -> hipError_t {
                 hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
                                               bt->stream);
                 if (e != hipSuccess) return e;
-                return run_pass(bt->stream, P, g.NT, c.dtype, g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, thr,
+                return run_pass(bt->stream, P, g.NT, c.dtype, c.precision, g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, thr,
                                 want_cond, fp64_pass, c.normalise != 0, bt->ctr, nullptr);
             };
             if (bt->use_graphs) {
-                const auto key = std::make_tuple(slot, nsd, L, S, pmax);
+                const auto key = std::make_tuple(slot, nsd, L, S, pmax, vec4);
                 auto it = g.graphs.find(key);
                 if (it == g.graphs.end()) {
                     hipGraph_t graph;

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/erx.h"
+
 namespace erx {
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_U16 = 2 };
@@ -43,9 +45,10 @@ struct Pass {
     int nseg;              // scan segments in the pass
     int seg;               // lines per scan segment
     int pmax;              // largest pixel count (sizes the score grid)
+    int vec4;              // every stream of the pass has a band count divisible by 4
 };
 
-hipError_t launch_gram(int dtype, const Pass& P, int NT, double* stats, hipStream_t s);
+hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s);
 hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,

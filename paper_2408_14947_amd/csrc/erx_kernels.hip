@@ -63,45 +63,41 @@ __device__ __forceinline__ V mma_xty(V acc, const V x, const V y)
 }
 
 // ---------------------------------------------------------------- input loads
+// Pointers that reach a kernel inside the pass descriptors are generic; the
+// memory behind them is always device global memory, and accessing it through
+// global-address-space pointers gives global (not flat) instructions, whose
+// completion is tracked separately from LDS traffic.
+#define GLB __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+// copy of a pass descriptor from global memory (class types cannot be copied
+// out of a global-address-space lvalue directly)
+__device__ __forceinline__ StreamDesc load_desc(const StreamDesc* p)
+{
+    static_assert(sizeof(StreamDesc) % 16 == 0, "descriptor size");
+    u4v w[sizeof(StreamDesc) / 16];
+    const GLB u4v* q = (const GLB u4v*)glb(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(StreamDesc) / 16); ++i) w[i] = q[i];
+    StreamDesc d;
+    __builtin_memcpy(&d, w, sizeof d);
+    return d;
+}
+
 template <int DT> __device__ __forceinline__ float ld1(const void* X, size_t i);
 template <> __device__ __forceinline__ float ld1<DT_F32>(const void* X, size_t i)
 {
-    return ((const float*)X)[i];
+    return glb((const float*)X)[i];
 }
 template <> __device__ __forceinline__ float ld1<DT_F16>(const void* X, size_t i)
 {
-    return __half2float(((const __half*)X)[i]);
+    return __half2float(__ushort_as_half(glb((const unsigned short*)X)[i]));
 }
 template <> __device__ __forceinline__ float ld1<DT_U16>(const void* X, size_t i)
 {
-    return (float)((const uint16_t*)X)[i] * (1.0f / 65536.0f);  // exact
-}
-
-// four consecutive bands [band0, band0+4) of one pixel row; bands >= b read 0
-template <int DT>
-__device__ __forceinline__ f4 ld4(const void* X, size_t row, int band0, int b)
-{
-    f4 v;
-    if (band0 + 4 <= b && (b & 3) == 0) {
-        const size_t i = row + band0;
-        if (DT == DT_F32) {
-            v = *(const f4*)((const float*)X + i);
-        } else if (DT == DT_F16) {
-            const uint2 u = *(const uint2*)((const __half*)X + i);
-            const __half2 h0 = *(const __half2*)&u.x, h1 = *(const __half2*)&u.y;
-            const float2 a = __half22float2(h0), c = __half22float2(h1);
-            v = f4{a.x, a.y, c.x, c.y};
-        } else {
-            const uint2 u = *(const uint2*)((const uint16_t*)X + i);
-            const float s = 1.0f / 65536.0f;
-            v = f4{(float)(u.x & 0xffffu) * s, (float)(u.x >> 16) * s,
-                   (float)(u.y & 0xffffu) * s, (float)(u.y >> 16) * s};
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (band0 + q < b) ? ld1<DT>(X, row + band0 + q) : 0.0f;
-    }
-    return v;
+    return (float)glb((const uint16_t*)X)[i] * (1.0f / 65536.0f);  // exact
 }
 
 template <int DT> __device__ __forceinline__ const void* advance(const void* x, size_t elems)
@@ -113,26 +109,28 @@ template <int DT> __device__ __forceinline__ const void* advance(const void* x, 
 __device__ __forceinline__ StreamDesc stream_of_line(const Pass& P, int line)
 {
     if (!P.sd) return P.one;
+    const GLB StreamDesc* sd = glb(P.sd);
     int lo = 0, hi = P.nstreams - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (P.sd[mid].line0 <= line) lo = mid;
+        if (sd[mid].line0 <= line) lo = mid;
         else hi = mid - 1;
     }
-    return P.sd[lo];
+    return load_desc(P.sd + lo);
 }
 
 // the stream owning pass scan segment `g`
 __device__ __forceinline__ StreamDesc stream_of_seg(const Pass& P, int g)
 {
     if (!P.sd) return P.one;
+    const GLB StreamDesc* sd = glb(P.sd);
     int lo = 0, hi = P.nstreams - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (P.sd[mid].seg0 <= g) lo = mid;
+        if (sd[mid].seg0 <= g) lo = mid;
         else hi = mid - 1;
     }
-    return P.sd[lo];
+    return load_desc(P.sd + lo);
 }
 
 __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile I <= J
@@ -140,85 +138,380 @@ __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile
     return (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
 }
 
+__device__ __forceinline__ int tile_lc(int J, int K, int NT)  // lower tile J >= K, column-major
+{
+    return K * NT - K * (K - 1) / 2 + (J - K);
+}
+
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+template <int PREC> struct LP;
+template <> struct LP<ERX_GRAM_BF16> {
+    typedef bf4 v4;
+    typedef bf8 v8;
+    static __device__ __forceinline__ f4 mma(v8 a, v8 b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct LP<ERX_GRAM_FP16> {
+    typedef h4 v4;
+    typedef h8 v8;
+    static __device__ __forceinline__ f4 mma(v8 a, v8 b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Four consecutive elements [i, i+4) of a line as FP32, with no branches.  With
+// VEC (b % 4 == 0 and i % 4 == 0) one 8- or 16-byte load; otherwise element
+// loads, where the caller passes ok[q] = false for elements that do not exist:
+// their offset is clamped to 0 (in bounds) and the caller ignores the value.
+// A load under a divergent branch, or a use right after it, makes the compiler
+// wait for every load in flight, so callers mask the values where they use
+// them, not here.
+template <int DT, bool VEC>
+__device__ __forceinline__ f4 ldq(const void* X, size_t i, int b_left)
+{
+    f4 v;
+    if (VEC) {
+        if (DT == DT_F32) {
+            v = *(const GLB f4*)glb((const float*)X + i);
+        } else if (DT == DT_F16) {
+            const u2v uv = *(const GLB u2v*)glb((const __half*)X + i);
+            const uint2 u = make_uint2(uv.x, uv.y);
+            const float2 a = __half22float2(*(const __half2*)&u.x), c = __half22float2(*(const __half2*)&u.y);
+            v = f4{a.x, a.y, c.x, c.y};
+        } else {
+            const u2v u = *(const GLB u2v*)glb((const uint16_t*)X + i);
+            const float sc = 1.0f / 65536.0f;
+            v = f4{(float)(u.x & 0xffffu) * sc, (float)(u.x >> 16) * sc, (float)(u.y & 0xffffu) * sc,
+                   (float)(u.y >> 16) * sc};
+        }
+    } else {
+        // b_left: elements of the row from i on (<= 0 when i itself is clamped)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = ld1<DT>(X, q < b_left ? i + q : 0);
+    }
+    return v;
+}
+
 // ============================================================================
 // Gram: per line, mean and centred covariance (Sec. III-C, Eqs. (18)-(19)).
 //
 // A workgroup of 4 waves computes one 64x64 block ("macro tile", 4x4 tiles of
 // 16 bands) of the upper triangle of the band x band Gram matrix of one line;
-// wave w owns tile row 4*MI+w.  Pixels are the contraction index.
+// wave w owns tile row 4*MI+w.  Pixels are the contraction index.  Grid:
+// 8 * ceil(n/8) * nmacro workgroups; block ids are spread so that all macro
+// tiles of one line run on the same XCD (consecutive block ids are dispatched
+// round-robin over the 8 XCDs) and share its L2.
 //
-// Data are shifted by s = the FP32 mean of the first min(64, p) pixels of each
-// band (the same value in every workgroup).  Chunks of GCH pixels of the 64
-// row bands and the 64 column bands are loaded with 16-byte loads (one chunk
-// ahead, in registers), shifted, and stored transposed in LDS (band-major,
-// pixels contiguous), so that one 16-byte LDS read gives a lane the operands
-// of four consecutive MFMA k-steps.  Products are accumulated on FP32 MFMA
-// over 64-pixel chunks and the chunk partials are summed in FP64; the exact
-// identity
+// Data are shifted by s = the FP32 mean of the first min(64, p) pixels of
+// each band (the same value in every workgroup), and the exact identity
 //     sum (x-mu)(x-mu)^T = sum (x-s)(x-s)^T - p (mu-s)(mu-s)^T
 // turns the shifted sums into the centred covariance.
 //
-// Grid: 8 * ceil(n/8) * nmacro workgroups; block ids are spread so that all
-// macro tiles of one line run on the same XCD (consecutive block ids are
-// dispatched round-robin over the 8 XCDs) and share its L2.
+// Operand precision (PREC):
+//   FP32         16x16x4 FP32 MFMA, FP32 partials over 64 pixels, FP64 sums.
+//   BF16 / FP16  a stated change to the method's arithmetic: x - s is rounded
+//                to 16 bits and multiplied on the 16x16x32 instructions with
+//                FP32 accumulation over 256 pixels, FP64 sums.  The score
+//                error grows from FP32 rounding to the 16-bit input rounding
+//                (2^-9 relative for BF16, 2^-12 for FP16), amplified by the
+//                conditioning of the covariance.  The band sums that give the
+//                mean are taken from the FP32 values, so the mean keeps FP32
+//                accuracy.  FP16 operands need |x - s| < 65504.
+//
+// Staging.  A chunk is 64 pixels.  Thread (bg, pq) = (tid % 16, tid / 16)
+// loads pixels 4pq..4pq+3 of the bands 4bg..4bg+3 of each panel, so the 16
+// consecutive lanes with equal pq read one contiguous 256-byte segment of a
+// pixel row.  All loads are unconditional (addresses of missing pixels and
+// bands are clamped into the line and their values zeroed afterwards): a load
+// under a divergent branch makes the compiler wait for every load already in
+// flight, which would serialise the one-chunk-ahead prefetch.  The thread
+// holds a 4 x 4 block (pixels x bands); transposed in registers, each band
+// row of 4 pixels is one 16-byte (FP32) or 8-byte (16-bit) LDS store.
+//
+// LDS holds band rows of 64 pixels.  FP32 rows are 16 quads of 4 pixels; the
+// quad index is XOR-swizzled with sw(r) = (r mod 16) xor (r div 16), so that
+// both the 16 lanes of a store (16 band groups) and the 16 lanes of an MFMA
+// operand read (16 consecutive band rows) hit 16 different 16-byte bank
+// groups.  16-bit rows are 8 octets of 8 pixels, swizzled with (r div 2) mod 8.
+// A lane (g, c) of an operand reads consecutive pixels of band c; A and B use
+// the same pixel order, so each step contracts over all of its pixels
+// whatever order the instruction pairs them in.
+//
+// Band sums for the mean are FP32 per thread over 4 pixels per chunk, FP64
+// across chunks and threads.
 // ============================================================================
-constexpr int GCH = 32;           // pixels per LDS chunk
-constexpr int GTS = GCH + 4;      // LDS stride of one band row (floats), 16-byte aligned
-constexpr int GSR = 16 * GCH / 256;  // float4 per thread per panel and chunk
-constexpr int GSG = 256 / GCH;       // band-group stride between a thread's float4
+__device__ __forceinline__ int g4_sw(int r) { return (r & 15) ^ (r >> 4); }
+__device__ __forceinline__ int g4_sw8(int r) { return (r >> 1) & 7; }
 
-// four consecutive bands of one pixel row; bands >= b read 0.  With
-// vec_ok (b % 4 == 0, band0 % 4 == 0) the four bands are all valid or all
-// invalid, so one predicated 16-byte (8-byte) load serves.
-template <int DT>
-__device__ __forceinline__ f4 ld4_any(const void* X, size_t row, int band0, int b, bool vec_ok)
-{
-    f4 v = f4{0.f, 0.f, 0.f, 0.f};
-    if (vec_ok) {
-        if (band0 >= b) return v;
-        const size_t i = row + band0;
-        if (DT == DT_F32) {
-            v = *(const f4*)((const float*)X + i);
-        } else if (DT == DT_F16) {
-            const uint2 u = *(const uint2*)((const __half*)X + i);
-            const float2 a = __half22float2(*(const __half2*)&u.x), c = __half22float2(*(const __half2*)&u.y);
-            v = f4{a.x, a.y, c.x, c.y};
-        } else {
-            const uint2 u = *(const uint2*)((const uint16_t*)X + i);
-            const float s = 1.0f / 65536.0f;
-            v = f4{(float)(u.x & 0xffffu) * s, (float)(u.x >> 16) * s, (float)(u.y & 0xffffu) * s,
-                   (float)(u.y >> 16) * s};
+template <int PREC> struct G4;
+template <> struct G4<ERX_GRAM_FP32> {
+    static constexpr int WORDS = 64 * 64;  // 32-bit words per panel
+    static constexpr int FLUSH = 64;       // pixels per FP32 partial
+    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v)
+    {
+        *(f4*)&T[r * 64 + 4 * (pq ^ g4_sw(r))] = v;
+    }
+    template <int NQ>
+    static __device__ __forceinline__ void chunk(const uint32_t* Rt, const uint32_t* Cp, int w, int c, int g,
+                                                 int kend, f4* acc)
+    {
+        const int ra = 16 * w + c;
+        for (int u = 0; u < kend; u += 16) {
+            const int qd = (u >> 2) + g;
+            const f4 av = *(const f4*)&Rt[ra * 64 + 4 * (qd ^ g4_sw(ra))];
+            f4 bv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int rb = 16 * q + c;
+                bv[q] = *(const f4*)&Cp[rb * 64 + 4 * (qd ^ g4_sw(rb))];
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc[q] = mfma(av[st], bv[q][st], acc[q]);
         }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (band0 + q < b) ? ld1<DT>(X, row + band0 + q) : 0.0f;
     }
-    return v;
+};
+template <int PREC> struct G4H {
+    typedef typename LP<PREC>::v4 v4;
+    typedef typename LP<PREC>::v8 v8;
+    static constexpr int WORDS = 64 * 32;
+    static constexpr int FLUSH = 256;
+    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v)
+    {
+        uint16_t* H = (uint16_t*)T;
+        *(v4*)&H[r * 64 + 8 * ((pq >> 1) ^ g4_sw8(r)) + 4 * (pq & 1)] = __builtin_convertvector(v, v4);
+    }
+    template <int NQ>
+    static __device__ __forceinline__ void chunk(const uint32_t* Rt, const uint32_t* Cp, int w, int c, int g,
+                                                 int kend, f4* acc)
+    {
+        const uint16_t* RH = (const uint16_t*)Rt;
+        const uint16_t* CH = (const uint16_t*)Cp;
+        const int ra = 16 * w + c;
+        for (int u = 0; u < kend; u += 32) {
+            const int oc = (u >> 3) + g;
+            const v8 av = *(const v8*)&RH[ra * 64 + 8 * (oc ^ g4_sw8(ra))];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int rb = 16 * q + c;
+                const v8 bv = *(const v8*)&CH[rb * 64 + 8 * (oc ^ g4_sw8(rb))];
+                acc[q] = LP<PREC>::mma(av, bv, acc[q]);
+            }
+        }
+    }
+};
+template <> struct G4<ERX_GRAM_BF16> : G4H<ERX_GRAM_BF16> {};
+template <> struct G4<ERX_GRAM_FP16> : G4H<ERX_GRAM_FP16> {};
+
+// The part of a macro tile's work that depends on whether it is diagonal (one
+// panel, rows = columns) is compiled separately for both cases, so that no
+// load sits under a branch.
+template <int DT, int PREC, bool VEC, bool DG>
+__device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT, int MI, int MJ, int line,
+                                            double* __restrict__ stats, long long E, uint32_t* Rt, uint32_t* Ct,
+                                            float* shift_s, double* red_s, double* bsum_s)
+{
+    typedef G4<PREC> G;
+    constexpr bool dg = DG;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int I = 4 * MI + w;
+    const bool rowok = I < NT;
+    const int rb0 = 64 * MI, cb0 = 64 * MJ;
+
+    const int bg = tid & 15, pq = tid >> 4;
+    // bands of this thread that exist (missing bands are zero in the products)
+    const int rband = rb0 + 4 * bg, cband = cb0 + 4 * bg;
+    bool rok[4], cok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        rok[j] = rband + j < b;
+        cok[j] = cband + j < b;
+    }
+    f4 pr[4], pc[4];
+    // unconditional: past the last pixel the addresses are clamped into the
+    // line and the values are masked by stage()
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int px = k0 + 4 * pq + r;
+            const bool okp = px < p;
+            const size_t row = (size_t)(okp ? px : 0) * b;
+            const bool okr = okp && rok[0], okc = okp && cok[0];
+            pr[r] = ldq<DT, VEC>(X, okr ? row + rband : 0, okr ? b - rband : 0);
+            if (!dg) pc[r] = ldq<DT, VEC>(X, okc ? row + cband : 0, okc ? b - cband : 0);
+        }
+    };
+    fetch(0);
+    {
+        // shift from the first chunk: per-thread sums of 4 pixels, then the 4
+        // pixel quads of a wave (lanes bg + 16k), then the 4 waves via LDS
+        const int nv0 = p - 4 * pq;
+        float a[4], e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] = e[j] = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a[j] += (r < nv0 && rok[j]) ? pr[r][j] : 0.f;
+                if (!dg) e[j] += (r < nv0 && cok[j]) ? pc[r][j] : 0.f;
+            }
+            if (dg) e[j] = a[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] += __shfl_xor(a[j], 16);
+            a[j] += __shfl_xor(a[j], 32);
+            e[j] += __shfl_xor(e[j], 16);
+            e[j] += __shfl_xor(e[j], 32);
+        }
+        float* part = (float*)Rt;  // [4 waves][128 bands], before the first stage
+        if (lane < 16)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                part[w * 128 + 4 * bg + j] = a[j];
+                part[w * 128 + 64 + 4 * bg + j] = e[j];
+            }
+        __syncthreads();
+        if (tid < 128) {
+            const float inv0 = 1.0f / (float)(p < 64 ? p : 64);
+            shift_s[tid] = ((part[tid] + part[128 + tid]) + (part[256 + tid] + part[384 + tid])) * inv0;
+        }
+        __syncthreads();
+    }
+    float shr[4], shc[4], sr[4], sc[4];
+    double dsr[4], dsc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        shr[j] = shift_s[4 * bg + j];
+        shc[j] = shift_s[64 + 4 * bg + j];
+        sr[j] = sc[j] = 0.f;
+        dsr[j] = dsc[j] = 0.0;
+    }
+    auto stage = [&](int k0) __attribute__((always_inline)) {
+        const int nv = p - k0 - 4 * pq;  // valid pixels among this thread's four
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            f4 v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = (r < nv && rok[j]) ? pr[r][j] - shr[j] : 0.f;
+            sr[j] += (v[0] + v[1]) + (v[2] + v[3]);
+            G::put(Rt, 4 * bg + j, pq, v);
+            if (!dg) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = (r < nv && cok[j]) ? pc[r][j] - shc[j] : 0.f;
+                sc[j] += (v[0] + v[1]) + (v[2] + v[3]);
+                G::put(Ct, 4 * bg + j, pq, v);
+            }
+        }
+    };
+    const uint32_t* Cp = dg ? (const uint32_t*)Rt : (const uint32_t*)Ct;
+
+    const int nq = __builtin_amdgcn_readfirstlane((NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4);
+    int tbits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tbits |= (rowok && (4 * MJ + q) < NT && (!dg || q >= w)) ? (1 << q) : 0;
+    tbits = __builtin_amdgcn_readfirstlane(tbits);
+
+    double S[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S[q][i] = 0.0;
+    f4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < p; k0 += 64) {
+        stage(k0);
+        __syncthreads();
+        fetch(k0 + 64);  // next chunk in flight during the products
+        if (rowok) {
+            const int kend = (p - k0) < 64 ? (p - k0) : 64;
+            switch (nq) {
+            case 1: G::template chunk<1>(Rt, Cp, w, c, g, kend, acc); break;
+            case 2: G::template chunk<2>(Rt, Cp, w, c, g, kend, acc); break;
+            case 3: G::template chunk<3>(Rt, Cp, w, c, g, kend, acc); break;
+            default: G::template chunk<4>(Rt, Cp, w, c, g, kend, acc); break;
+            }
+        }
+        if (((k0 + 64) % G::FLUSH) == 0 || k0 + 64 >= p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) S[q][i] += (double)acc[q][i];
+                acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dsr[j] += (double)sr[j];
+                dsc[j] += (double)sc[j];
+                sr[j] = sc[j] = 0.f;
+            }
+        }
+        __syncthreads();
+    }
+
+    // band sums: the 4 pixel quads of a wave, then the 4 waves
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        dsr[j] += __shfl_xor(dsr[j], 16);
+        dsr[j] += __shfl_xor(dsr[j], 32);
+        dsc[j] += __shfl_xor(dsc[j], 16);
+        dsc[j] += __shfl_xor(dsc[j], 32);
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            red_s[w * 128 + 4 * bg + j] = dsr[j];
+            red_s[w * 128 + 64 + 4 * bg + j] = dsc[j];
+        }
+    __syncthreads();
+    if (tid < 128) {
+        const int t = (dg && tid >= 64) ? tid - 64 : tid;
+        bsum_s[tid] = (red_s[t] + red_s[128 + t]) + (red_s[256 + t] + red_s[384 + t]);
+    }
+    __syncthreads();
+    if (!rowok) return;
+
+    const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
+    double* ls = stats + (size_t)line * E;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!(tbits & (1 << q))) continue;
+        const double scol = bsum_s[64 + 16 * q + c];
+        double o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double srho = bsum_s[16 * w + 4 * g + i];
+            o[i] = (S[q][i] - srho * scol * inv_p) * inv_p1;
+        }
+        double* dst = ls + tile_u(I, 4 * MJ + q, NT) * 256 + lane * 4;
+        *(double2*)dst = double2{o[0], o[1]};
+        *(double2*)(dst + 2) = double2{o[2], o[3]};
+    }
+    if (dg && g == 0) {
+        const long long ntU = (long long)NT * (NT + 1) / 2;
+        const int band = 16 * I + c;
+        ls[ntU * 256 + band] = (band < b) ? (double)shift_s[16 * w + c] + bsum_s[16 * w + c] * inv_p : 0.0;
+    }
 }
 
-// MFMA products of one LDS chunk for NQ column tiles (unconditional, so the
-// accumulators stay in place): lane group g supplies pixels u+4g..u+4g+3 for
-// the four k-steps of each 16-pixel group.
-template <int NQ>
-__device__ __forceinline__ void gram_chunk(const float* Rt, const float* Cp, int w, int c, int g, int kend,
-                                           f4* acc)
-{
-    for (int u = 0; u < kend; u += 16) {
-        const f4 av = *(const f4*)&Rt[(16 * w + c) * GTS + u + 4 * g];
-        f4 bv[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) bv[q] = *(const f4*)&Cp[(16 * q + c) * GTS + u + 4 * g];
-#pragma unroll
-        for (int st = 0; st < 4; ++st)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] = mfma(av[st], bv[q][st], acc[q]);
-    }
-}
 
-template <int DT>
-__global__ __launch_bounds__(256) void k_gram(const Pass P, int NT, int nmacro, double* __restrict__ stats,
-                                              long long E)
+template <int DT, int PREC, bool VEC>
+__global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro, double* __restrict__ stats,
+                                               long long E)
 {
+    typedef G4<PREC> G;
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int kk = bid >> 3;
@@ -236,148 +529,15 @@ __global__ __launch_bounds__(256) void k_gram(const Pass P, int NT, int nmacro, 
         ++MI;
     }
     const int MJ = MI + m;
-    const bool dg = (MI == MJ);
-    const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lane = tid & 63, g = lane >> 4, c = lane & 15;
-    const int I = 4 * MI + w;  // this wave's tile row
-    const bool rowok = I < NT;
-    const int rb0 = 64 * MI, cb0 = 64 * MJ;  // first band of the row / column panels
-
-    __shared__ __attribute__((aligned(16))) float Rt[64 * GTS];  // [band][pixel]
-    __shared__ __attribute__((aligned(16))) float Ct[64 * GTS];
+    __shared__ __attribute__((aligned(16))) uint32_t Rt[G::WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t Ct[G::WORDS];
     __shared__ float shift_s[128];
+    __shared__ double red_s[4 * 128];
     __shared__ double bsum_s[128];
-
-    const size_t lbase = 0;
-    const bool vec_ok = (b & 3) == 0;
-    // staging map: a panel chunk is GCH pixels x 16 groups of 4 bands; thread
-    // tid handles pixel tid % GCH of band groups tid / GCH + GSG * r, so that
-    // consecutive lanes write consecutive LDS words
-    const int spx = tid % GCH, sg0 = tid / GCH;
-    f4 pr[GSR], pc[GSR];
-    auto fetch = [&](int k0) __attribute__((always_inline)) {
-        const int px = k0 + spx;
-        const bool okp = px < p;
-        const size_t row = lbase + (size_t)(okp ? px : 0) * b;
-#pragma unroll
-        for (int r = 0; r < GSR; ++r) {
-            const int b4 = 4 * (sg0 + GSG * r);
-            pr[r] = okp ? ld4_any<DT>(X, row, rb0 + b4, b, vec_ok) : f4{0.f, 0.f, 0.f, 0.f};
-            if (!dg) pc[r] = okp ? ld4_any<DT>(X, row, cb0 + b4, b, vec_ok) : f4{0.f, 0.f, 0.f, 0.f};
-        }
-    };
-
-    // shift from the first min(64, p) pixels, summed in pixel order
-    const int p0 = p < 64 ? p : 64;
-    if (tid < 128) {
-        const int col = tid & 63;
-        const int band = (tid < 64 ? rb0 : cb0) + col;
-        float sum = 0.f;
-        if (band < b)
-            for (int k = 0; k < p0; ++k) sum += ld1<DT>(X, lbase + (size_t)k * b + band);
-        shift_s[tid] = (band < b) ? sum / (float)p0 : 0.f;
-    }
-    fetch(0);
-    __syncthreads();
-    auto stage = [&](int k0) __attribute__((always_inline)) {
-        const bool okp = k0 + spx < p;
-#pragma unroll
-        for (int r = 0; r < GSR; ++r)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int band = 4 * (sg0 + GSG * r) + j;
-                Rt[band * GTS + spx] = okp ? pr[r][j] - shift_s[band] : 0.f;
-                if (!dg) Ct[band * GTS + spx] = okp ? pc[r][j] - shift_s[64 + band] : 0.f;
-            }
-    };
-    // band sums of the shifted values: thread tid sums band (tid & 63) of panel
-    // (tid >> 6) & 1 over half (tid >> 7) of each chunk, straight from LDS
-    const int sband = tid & 63, spanel = (tid >> 6) & 1, shalf = tid >> 7;
-    const float* sumsrc = (spanel && !dg) ? Ct : Rt;
-    double bpart = 0.0;
-    const float* Cp = dg ? Rt : Ct;
-
-    // column tiles of this macro (the lower tiles of a diagonal macro are
-    // computed with the others and simply not stored)
-    const int nq = __builtin_amdgcn_readfirstlane((NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4);
-    int tbits = 0;  // column tiles this wave stores (wave-uniform)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) tbits |= (rowok && (4 * MJ + q) < NT && (!dg || q >= w)) ? (1 << q) : 0;
-    tbits = __builtin_amdgcn_readfirstlane(tbits);
-
-    double S[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) S[q][i] = 0.0;
-    f4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < p; k0 += GCH) {
-        stage(k0);
-        __syncthreads();
-        if (k0 + GCH < p) fetch(k0 + GCH);  // prefetch the next chunk into registers
-        {
-            const float* rowp = sumsrc + sband * GTS + (GCH / 2) * shalf;
-            float ps = 0.f;
-#pragma unroll
-            for (int q = 0; q < GCH / 8; ++q) {
-                const f4 v = *(const f4*)(rowp + 4 * q);
-                ps += (v[0] + v[1]) + (v[2] + v[3]);
-            }
-            bpart += (double)ps;
-        }
-        if (rowok) {
-            const int kend = (p - k0) < GCH ? (p - k0) : GCH;
-            switch (nq) {
-            case 1: gram_chunk<1>(Rt, Cp, w, c, g, kend, acc); break;
-            case 2: gram_chunk<2>(Rt, Cp, w, c, g, kend, acc); break;
-            case 3: gram_chunk<3>(Rt, Cp, w, c, g, kend, acc); break;
-            default: gram_chunk<4>(Rt, Cp, w, c, g, kend, acc); break;
-            }
-        }
-        // FP64 sums of the FP32 partials every 64 pixels and at the end
-        if (((k0 + GCH) & 63) == 0 || k0 + GCH >= p) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) S[q][i] += (double)acc[q][i];
-                acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-            }
-        }
-        __syncthreads();  // LDS is rewritten by the next chunk
-    }
-
-    // band sums: add the two halves
-    if (shalf == 1) bsum_s[spanel * 64 + sband] = bpart;
-    __syncthreads();
-    if (shalf == 0) bsum_s[spanel * 64 + sband] += bpart;
-    __syncthreads();
-    if (!rowok) return;
-
-    const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
-    double* ls = stats + (size_t)line * E;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (!(tbits & (1 << q))) continue;
-        const double scol = bsum_s[(dg ? 0 : 64) + 16 * q + c];
-        double o[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double srho = bsum_s[16 * w + 4 * g + i];  // sum of row band 16I+4g+i
-            o[i] = (S[q][i] - srho * scol * inv_p) * inv_p1;
-        }
-        double* dst = ls + tile_u(I, 4 * MJ + q, NT) * 256 + lane * 4;
-        *(double2*)dst = double2{o[0], o[1]};
-        *(double2*)(dst + 2) = double2{o[2], o[3]};
-    }
-    if (dg && g == 0) {
-        const long long ntU = (long long)NT * (NT + 1) / 2;
-        const int band = 16 * I + c;
-        ls[ntU * 256 + band] = (band < b) ? (double)shift_s[16 * w + c] + bsum_s[16 * w + c] * inv_p : 0.0;
-    }
+    if (MI == MJ)
+        gram4_macro<DT, PREC, VEC, true>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s);
+    else
+        gram4_macro<DT, PREC, VEC, false>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s);
 }
 
 // ============================================================================
@@ -434,8 +594,9 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
 {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= E) return;
-    const StreamDesc d = P.sd ? P.sd[blockIdx.y] : P.one;
-    double cv = d.state[e];
+    const StreamDesc d = P.sd ? load_desc(P.sd + blockIdx.y) : P.one;
+    GLB double* state = glb(d.state);
+    double cv = state[e];
     const int nseg = (d.n + P.seg - 1) / P.seg;
     for (int gs = 0; gs < nseg; ++gs) {
         carry[(size_t)(d.seg0 + gs) * E + e] = cv;
@@ -443,7 +604,7 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
         const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
         cv = seg_decay(d.t0, l0, l1, d.alpha) * cv + stats[(size_t)(d.line0 + l1 - 1) * E + e];
     }
-    d.state[e] = cv;
+    state[e] = cv;
 }
 
 // ============================================================================
@@ -764,7 +925,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
             if (tI[j] < 0) continue;
-            const int s = tI[j] * (tI[j] + 1) / 2 + tJ[j];
+            const int s = tile_lc(tI[j], tJ[j], NT);  // column-major, as the score kernel reads them
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int off = 64 * (c >> 2) + 4 * rowof<T>(g, i) + (c & 3);
@@ -941,28 +1102,65 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
 // Score (Sec. III-D, Eqs. (22)-(23)): for each pixel, r = x - mu_t, m = M r
 // with M = L_t^{-1} lower triangular, delta = ||m||.  Y_J = sum_{K<=J} M_JK R_K
 // for 16-pixel column tiles R_K (bands 16K..16K+15) on FP32 MFMA: the M^T
-// tiles are read in operand form and R_K is four consecutive bands of one
+// tiles are held in operand form and R_K is four consecutive bands of one
 // pixel per lane, which is exactly the accumulator-layout operand of X^T Y.
-// Each wave scores PT tiles of 16 pixels; a workgroup is 4 waves.
+//
+// A workgroup of 4 waves scores 4 * PT tiles of 16 pixels of one line.  The
+// M^T tiles are stored column by column (all tiles (J, K), J >= K, of column
+// K contiguous); the workgroup stages column K in LDS (double-buffered, the
+// next column's global loads in flight during the products of this one), so
+// each tile is read from L2 once per workgroup rather than once per wave.  The
+// pixel data of the next column is prefetched into registers the same way.
 // ============================================================================
-template <int NT, int DT>
+template <int NT, int DT, bool VEC>
 __global__ __launch_bounds__(256) void k_score(const Pass P, const float* __restrict__ Mt,
                                                const float* __restrict__ mu32, int ngrp)
 {
     constexpr int NTL = NT * (NT + 1) / 2;
     constexpr int PT = SCORE_PT;
+    constexpr int MR = (NT * 64 + 255) / 256;  // float4 per thread to stage the longest column
     const int line = blockIdx.x / ngrp, grp = blockIdx.x - line * ngrp;
-    if (line >= P.nlines) return;
+    if (line >= P.nlines) return;  // uniform for the workgroup
     const StreamDesc d = stream_of_line(P, line);
     const int p = d.p, b = d.b;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    // waves past the last pixel still stage tiles and meet the barriers
     const int pix0 = (grp * 4 + w) * PT * 16;
-    if (pix0 >= p) return;  // wave-uniform; the kernel has no barrier
     const void* X = advance<DT>(d.x, (size_t)(line - d.line0) * p * b);
-    float* out = d.out + (size_t)(line - d.line0) * p;
+    GLB float* out = glb(d.out + (size_t)(line - d.line0) * p);
     const float* mu = mu32 + (size_t)line * 16 * NT;
-    const float* Ml = Mt + (size_t)line * NTL * 256 + lane * 4;
-    const size_t lrow = 0;
+    const f4* Ml = (const f4*)(Mt + (size_t)line * NTL * 256);
+
+    __shared__ f4 Ms[2][NT * 64];
+    f4 st[MR];
+    auto gload = [&](int K) __attribute__((always_inline)) {
+        const int n = (NT - K) * 64;
+        const f4* src = Ml + (size_t)tile_lc(K, K, NT) * 64;
+#pragma unroll
+        for (int i = 0; i < MR; ++i) {
+            const int q = tid + 256 * i;
+            st[i] = src[q < n ? q : 0];
+        }
+    };
+    auto lstore = [&](int K, int buf) __attribute__((always_inline)) {
+        const int n = (NT - K) * 64;
+#pragma unroll
+        for (int i = 0; i < MR; ++i) {
+            const int q = tid + 256 * i;
+            if (q < n) Ms[buf][q] = st[i];
+        }
+    };
+    f4 y[2][PT];
+    auto yload = [&](int K, f4* yy) __attribute__((always_inline)) {
+        const int band0 = 16 * K + 4 * g;
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int pix = pix0 + 16 * t + c;
+            const bool okl = pix < p && band0 < b;
+            yy[t] = ldq<DT, VEC>(X, okl ? (size_t)pix * b + band0 : 0, okl ? b - band0 : 0);
+        }
+    };
 
     f4 acc[NT][PT];
 #pragma unroll
@@ -970,27 +1168,36 @@ __global__ __launch_bounds__(256) void k_score(const Pass P, const float* __rest
 #pragma unroll
         for (int t = 0; t < PT; ++t) acc[J][t] = f4{0.f, 0.f, 0.f, 0.f};
 
+    gload(0);
+    yload(0, y[0]);
+    lstore(0, 0);
+    __syncthreads();
 #pragma unroll
     for (int K = 0; K < NT; ++K) {
+        if (K + 1 < NT) {
+            gload(K + 1);
+            yload(K + 1, y[(K + 1) & 1]);
+        }
+        // residual of this column's bands: missing pixels and bands are zero
+        // (padded bands also have mu 0)
         const int band0 = 16 * K + 4 * g;
         const f4 m4 = *(const f4*)(mu + band0);
-        f4 y[PT];
+        f4 r[PT];
 #pragma unroll
         for (int t = 0; t < PT; ++t) {
-            const int pix = pix0 + 16 * t + c;
-            if (pix < p) {
-                y[t] = ld4<DT>(X, (lrow + pix) * (size_t)b, band0, b) - m4;
-                // padded bands read 0 and have mu 0
-            } else {
-                y[t] = f4{0.f, 0.f, 0.f, 0.f};
-            }
+            const bool okp = pix0 + 16 * t + c < p;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[t][q] = (okp && band0 + q < b) ? y[K & 1][t][q] - m4[q] : 0.f;
         }
+        const f4* Mc = Ms[K & 1];
 #pragma unroll
         for (int J = K; J < NT; ++J) {
-            const f4 xm = *(const f4*)(Ml + (J * (J + 1) / 2 + K) * 256);
+            const f4 xm = Mc[(J - K) * 64 + lane];
 #pragma unroll
-            for (int t = 0; t < PT; ++t) acc[J][t] = mma_xty(acc[J][t], xm, y[t]);
+            for (int t = 0; t < PT; ++t) acc[J][t] = mma_xty(acc[J][t], xm, r[t]);
         }
+        if (K + 1 < NT) lstore(K + 1, (K + 1) & 1);
+        __syncthreads();
     }
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
@@ -1002,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_score(const Pass P, const float* __rest
         ss += __shfl_xor(ss, 16);
         ss += __shfl_xor(ss, 32);
         const int pix = pix0 + 16 * t + c;
-        if (g == 0 && pix < p) out[lrow + pix] = sqrtf(ss);
+        if (g == 0 && pix < p) out[pix] = sqrtf(ss);
     }
 }
 
@@ -1017,8 +1224,8 @@ __global__ __launch_bounds__(256) void k_normalise(const Pass P)
     const StreamDesc d = stream_of_line(P, line);
     const int p = d.p;
     __shared__ double red[256];
-    const float* x = d.out + (size_t)(line - d.line0) * p;
-    float* dn = d.outn + (size_t)(line - d.line0) * p;
+    const GLB float* x = glb(d.out + (size_t)(line - d.line0) * p);
+    GLB float* dn = glb(d.outn + (size_t)(line - d.line0) * p);
     double s = 0.0;
     for (int i = threadIdx.x; i < p; i += 256) s += (double)x[i];
     red[threadIdx.x] = s;
@@ -1067,17 +1274,34 @@ static int gram_macros(int NT)
     return MT * (MT + 1) / 2;
 }
 
-hipError_t launch_gram(int dtype, const Pass& P, int NT, double* stats, hipStream_t s)
+template <int PREC, bool VEC>
+static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const Pass& P, int NT, int nm,
+                         double* stats, long long E)
+{
+    switch (dtype) {
+    case DT_F32: hipLaunchKernelGGL((k_gram4<DT_F32, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E); break;
+    case DT_F16: hipLaunchKernelGGL((k_gram4<DT_F16, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E); break;
+    default: hipLaunchKernelGGL((k_gram4<DT_U16, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E); break;
+    }
+}
+
+template <int PREC>
+static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const Pass& P, int NT, int nm,
+                         double* stats, long long E)
+{
+    if (P.vec4) launch_gram4<PREC, true>(dtype, grid, block, s, P, NT, nm, stats, E);
+    else launch_gram4<PREC, false>(dtype, grid, block, s, P, NT, nm, stats, E);
+}
+
+hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s)
 {
     const int nm = gram_macros(NT);
     const long long E = stat_entries(NT);
     const long long nblk = (long long)((P.nlines + 7) / 8) * 8 * nm;
     dim3 grid((unsigned)nblk), block(256);
-    switch (dtype) {
-    case DT_F32: hipLaunchKernelGGL(k_gram<DT_F32>, grid, block, 0, s, P, NT, nm, stats, E); break;
-    case DT_F16: hipLaunchKernelGGL(k_gram<DT_F16>, grid, block, 0, s, P, NT, nm, stats, E); break;
-    default: hipLaunchKernelGGL(k_gram<DT_U16>, grid, block, 0, s, P, NT, nm, stats, E); break;
-    }
+    if (prec == ERX_GRAM_BF16) launch_gram4<ERX_GRAM_BF16>(dtype, grid, block, s, P, NT, nm, stats, E);
+    else if (prec == ERX_GRAM_FP16) launch_gram4<ERX_GRAM_FP16>(dtype, grid, block, s, P, NT, nm, stats, E);
+    else launch_gram4<ERX_GRAM_FP32>(dtype, grid, block, s, P, NT, nm, stats, E);
     return hipGetLastError();
 }
 
@@ -1141,8 +1365,9 @@ static void score_one(const Pass& P, const float* Mt, const float* mu32, hipStre
 {
     const int per = 4 * SCORE_PT * 16;
     const int ngrp = (P.pmax + per - 1) / per;
-    hipLaunchKernelGGL((k_score<NT, DT>), dim3((unsigned)((long long)P.nlines * ngrp)), dim3(256), 0, s, P, Mt,
-                       mu32, ngrp);
+    const dim3 grid((unsigned)((long long)P.nlines * ngrp));
+    if (P.vec4) hipLaunchKernelGGL((k_score<NT, DT, true>), grid, dim3(256), 0, s, P, Mt, mu32, ngrp);
+    else hipLaunchKernelGGL((k_score<NT, DT, false>), grid, dim3(256), 0, s, P, Mt, mu32, ngrp);
 }
 
 template <int DT, int... NTs>

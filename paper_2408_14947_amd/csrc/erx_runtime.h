@@ -41,7 +41,7 @@ struct Profiler {
 // Launch the whole hot path for one pass: per-line mean and Gram, segment
 // scan, carries, factorisation (FP32 with FP64 re-factor when thr > 0,
 // FP64 for every line when thr == 0), scores, optional normalisation.
-hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, double* stats, double* carry, float* Mt,
+hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, double* stats, double* carry, float* Mt,
                     float* mu32, int* flags, float* cond, double thr, int want_cond, bool fp64_pass,
                     bool normalise, unsigned long long* ctr, Profiler* prof);
 

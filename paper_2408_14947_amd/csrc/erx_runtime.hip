@@ -72,13 +72,13 @@ void Profiler::release()
     pool.clear();
 }
 
-hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, double* stats, double* carry, float* Mt,
+hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, double* stats, double* carry, float* Mt,
                     float* mu32, int* flags, float* cond, double thr, int want_cond, bool fp64_pass,
                     bool normalise, unsigned long long* ctr, Profiler* prof)
 {
     auto T = [&](int k, auto&& f) -> hipError_t { return prof ? prof->timed(s, k, f) : f(); };
     hipError_t e;
-    if ((e = T(K_GRAM, [&] { return launch_gram(dtype, P, NT, stats, s); })) != hipSuccess) return e;
+    if ((e = T(K_GRAM, [&] { return launch_gram(dtype, prec, P, NT, stats, s); })) != hipSuccess) return e;
     if ((e = T(K_SCAN_LOCAL, [&] { return launch_scan_local(P, NT, stats, s); })) != hipSuccess) return e;
     if ((e = T(K_SCAN_CARRY, [&] { return launch_scan_carry(P, NT, stats, carry, s); })) != hipSuccess) return e;
     if (thr > 0.0) {

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("field,value", [("bands", 0), ("bands", 305), ("pixels", 1),
                                          ("momentum", 0.0), ("momentum", 1.5),
                                          ("momentum", float("nan")), ("ridge", -1e-3),
-                                         ("dtype", 7), ("block_lines", 0), ("scan_lines", 0),
+                                         ("dtype", 7), ("precision", 3), ("block_lines", 0), ("scan_lines", 0),
                                          ("warmup", -1), ("fp64_cond_threshold", -1.0),
                                          ("cond_estimate", 2)])
 def test_create_rejects_invalid_config(field, value):
