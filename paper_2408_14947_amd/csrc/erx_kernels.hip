@@ -1113,7 +1113,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
 // pixel data of the next column is prefetched into registers the same way.
 // ============================================================================
 template <int NT, int DT, bool VEC>
-__global__ __launch_bounds__(256) void k_score(const Pass P, const float* __restrict__ Mt,
+__global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __restrict__ Mt,
                                                const float* __restrict__ mu32, int ngrp)
 {
     constexpr int NTL = NT * (NT + 1) / 2;
