@@ -168,6 +168,78 @@ def time_workload(erx, torch, X, b, p, momentum, steps, warmup, block_lines, str
     return ms, wall, prof, st
 
 
+def batched_leg(erx, torch, cfg, T, stream, mixed):
+    """Many independent streams of one workload configuration (each cut to T lines): the batched
+    path (shared passes, graph replay) against one handle per stream pushed one after another,
+    and optionally the mixed configuration (BF16 Gram, FP32 Cholesky with FP64 re-factor above a
+    condition estimate of 1e6) with its per-stream error against the plain batched scores."""
+    import datagen
+    scenes = datagen.config_scenes(cfg, scale_lines=T)
+    storage = scenes[0].storage
+    with torch.cuda.stream(stream):
+        data = [datagen.lines(sc, 0, sc.lines, device="cuda")[0] for sc in scenes]
+    torch.cuda.synchronize()
+    B = [sc.bands for sc in scenes]
+    Pp = [sc.pixels for sc in scenes]
+    A = [sc.momentum for sc in scenes]
+    n_lines = sum(x.shape[0] for x in data)
+    n_pix = sum(x.shape[0] * x.shape[1] for x in data)
+    in_bytes = sum(x.numel() * x.element_size() for x in data)
+
+    def timed(fn):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    def run_batch(**kw):
+        bt = erx.Batch(B, Pp, A, dtype=storage, block_lines=8192, stream=stream.cuda_stream, **kw)
+        bt.push(data)  # warm-up: captures the pass graphs
+        torch.cuda.synchronize()
+        bt2 = erx.Batch(B, Pp, A, dtype=storage, block_lines=8192, stream=stream.cuda_stream, **kw)
+        bt2.push(data)
+        torch.cuda.synchronize()
+        ms = timed(lambda: bt2.push(data))  # same lines again: the state continues, the work is the same
+        out = bt2.scores()
+        torch.cuda.synchronize()
+        bt.close()
+        bt2.close()
+        return ms, out
+
+    ms_b, ref = run_batch()
+    dets = [erx.Detector(b, p, a, dtype=storage, block_lines=max(x.shape[0], 1), stream=stream.cuda_stream)
+            for b, p, a, x in zip(B, Pp, A, data)]
+    for d, x in zip(dets, data):
+        d.push(x)
+    ms_1 = timed(lambda: [d.push(x) for d, x in zip(dets, data)])
+    for d in dets:
+        d.close()
+    res = {"workload": f"{datagen.CONFIGS[cfg]['name']}: {len(scenes)} streams x {T} lines, {storage}",
+           "streams": len(scenes), "lines": n_lines, "pixels": n_pix, "input_bytes": in_bytes,
+           "batched": {"ms": ms_b, "lines_per_s": n_lines / (ms_b / 1e3), "pixels_per_s": n_pix / (ms_b / 1e3),
+                       "hbm_gbs_in_plus_scores": (in_bytes + 4 * n_pix) / (ms_b / 1e3) / 1e9},
+           "one_handle_per_stream": {"ms": ms_1, "lines_per_s": n_lines / (ms_1 / 1e3),
+                                     "pixels_per_s": n_pix / (ms_1 / 1e3)},
+           "batched_speedup": ms_1 / ms_b}
+    res["batched"]["hbm_frac"] = res["batched"]["hbm_gbs_in_plus_scores"] / PEAK["hbm_gbs"]
+    if mixed:
+        ms_m, got = run_batch(precision="bf16", fp64_cond_threshold=1e6, cond_estimate=1)
+        per = []
+        for g, r in zip(got, ref):
+            e = ((g.double() - r.double()).abs() / r.double().abs().clamp_min(1.0)).flatten()
+            k = max(1, e.numel() // 100)
+            per.append((float(e.max()), float(torch.topk(e, k).values.min())))
+        res["mixed_bf16"] = {"ms": ms_m, "pixels_per_s": n_pix / (ms_m / 1e3), "speedup_vs_batched_plain": ms_b / ms_m,
+                             "err_vs_plain_worst_stream": {"max": max(a for a, _ in per), "p99": max(b for _, b in per)},
+                             "bound": {"max": MIXED_BOUNDS["bf16"][0], "p99": MIXED_BOUNDS["bf16"][1]}}
+    del data, ref
+    torch.cuda.empty_cache()
+    return res
+
+
 # frozen error bounds of the reduced-precision Gram (max, p99 of the relative score error)
 MIXED_BOUNDS = {"bf16": (1e-2, 3e-3), "fp16": (1e-3, 5e-4)}
 
@@ -229,6 +301,10 @@ def main():
     ap.add_argument("--no-108", action="store_true", help="skip the 108-band side measurement")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the reduced-precision (BF16 / FP16 Gram) side measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the many-stream side measurements (batched-u16, batched-multispectral-f16)")
+    ap.add_argument("--batched-lines", type=int, default=128,
+                    help="lines per stream in the many-stream side measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known traffic against "
                          "which the FETCH_SIZE / WRITE_SIZE counters are scaled)")
@@ -338,6 +414,11 @@ def main():
                             "lines_per_s": l1, "pixels_per_s": l1 * sc1.pixels,
                             "ms_per_pass": ms1 / max(args.steps, 10)}
         del X1
+
+    if not args.no_batched:
+        print("[bench] many-stream workloads", file=sys.stderr, flush=True)
+        out["batched_u16"] = batched_leg(erx, torch, 3, args.batched_lines, stream, mixed=True)
+        out["batched_multispectral_f16"] = batched_leg(erx, torch, 4, args.batched_lines, stream, mixed=False)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -28,7 +28,7 @@ EXPORTS = (
     "erx_push_lines_ex", "erx_scores", "erx_scores_device", "erx_scores_normalised", "erx_labels",
     "erx_get_state", "erx_set_state", "erx_stats", "erx_line_info", "erx_profile_enable",
     "erx_profile_read", "erx_batch_create", "erx_batch_set_stream", "erx_batch_push",
-    "erx_batch_scores", "erx_batch_get_state", "erx_batch_stats", "erx_batch_use_graphs",
+    "erx_batch_scores", "erx_batch_get_state", "erx_batch_stats", "erx_batch_use_graphs", "erx_batch_small_path",
     "erx_batch_synchronize", "erx_batch_destroy", "erx_synchronize", "erx_destroy", "erx_last_error",
 )
 
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
         "erx_batch_get_state": (ip, [vp, ip, C.POINTER(C.c_longlong), vp, vp]),
         "erx_batch_stats": (ip, [vp, C.POINTER(Stats)]),
         "erx_batch_use_graphs": (ip, [vp, ip]),
+        "erx_batch_small_path": (ip, [vp, ip]),
         "erx_batch_synchronize": (ip, [vp]),
         "erx_batch_destroy": (None, [vp]),
         "erx_synchronize": (ip, [vp]),
@@ -283,7 +284,7 @@ class Batch:
                  precision: str = "fp32",
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
                  scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True,
-                 stream: Optional[int] = -1):
+                 stream: Optional[int] = -1, small_path: int = -1):
         lib = load()
         self.bands = [int(x) for x in bands]
         self.pixels = [int(x) for x in pixels]
@@ -315,6 +316,7 @@ class Batch:
         if stream is not None:
             _check(lib.erx_batch_set_stream(self._h, C.c_void_p(stream)))
         _check(lib.erx_batch_use_graphs(self._h, 1 if graphs else 0))
+        _check(lib.erx_batch_small_path(self._h, int(small_path)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -242,8 +242,8 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
     if (rc) return rc;
     const bool dev = is_device_ptr(lines);
     const size_t esz = elem_size(c.dtype);
-    if (dev && ((uintptr_t)lines % (4 * esz)) != 0)
-        return fail(ERX_EINVAL, "device line buffer must be aligned to 4 elements (%zu bytes)", 4 * esz);
+    if (dev && ((uintptr_t)lines % esz) != 0)
+        return fail(ERX_EINVAL, "device line buffer must be aligned to its element size (%zu bytes)", esz);
     const size_t line_bytes = (size_t)c.pixels * c.bands * esz;
     const int C = c.block_lines, seg = c.scan_lines;
     if (!dev && !h->staging) {
@@ -286,7 +286,8 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.nseg = (nc + seg - 1) / seg;
         P.seg = seg;
         P.pmax = c.pixels;
-        P.vec4 = (c.bands % 4) == 0;
+        // 4-band vector loads need b % 4 == 0 and a 4-element aligned buffer
+        P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)src % (4 * esz)) == 0;
         HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, c.precision, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));

@@ -71,6 +71,7 @@ struct erx_batch {
     hipStream_t own_stream = nullptr;
     unsigned long long* ctr = nullptr;
     bool use_graphs = true;
+    int small_mode = -1;  // fused path for one-tile streams: -1 auto, 0 off, 1 on
     unsigned long long notpd_before = 0;
 };
 
@@ -220,6 +221,14 @@ int erx_batch_use_graphs(erx_batch* bt, int on)
     return ERX_OK;
 }
 
+int erx_batch_small_path(erx_batch* bt, int mode)
+{
+    if (!bt) return fail(ERX_EINVAL, "NULL batch");
+    if (mode < -1 || mode > 1) return fail(ERX_EINVAL, "small-path mode must be -1, 0 or 1");
+    bt->small_mode = mode;
+    return ERX_OK;
+}
+
 int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
 {
     if (!bt || !lines || !nlines) return fail(ERX_EINVAL, "NULL argument");
@@ -231,8 +240,8 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
         if (nlines[s] == 0) continue;
         if (!lines[s] || !device_ptr(lines[s]))
             return fail(ERX_EINVAL, "stream %d: the line buffer must be device memory", s);
-        if (((uintptr_t)lines[s] % (4 * esz)) != 0)
-            return fail(ERX_EINVAL, "stream %d: line buffer must be aligned to 4 elements", s);
+        if (((uintptr_t)lines[s] % esz) != 0)
+            return fail(ERX_EINVAL, "stream %d: line buffer must be aligned to its element size", s);
     }
     // result buffers
     for (int s = 0; s < ns; ++s) {
@@ -269,6 +278,45 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
     const int C = c.block_lines, seg = c.scan_lines;
 
     for (Group& g : bt->groups) {
+        if (g.NT == 1 && (bt->small_mode == 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
+            // fused path: one launch, every stream's lines in order
+            const int slot = g.next_slot;
+            g.next_slot = (g.next_slot + 1) % NSLOT;
+            HIPCHK(hipEventSynchronize(g.slot_ev[slot]));
+            StreamDesc* hd = g.h_sd[slot];
+            int nsd = 0, vec4 = 1, pmax = 0;
+            for (int s : g.streams) {
+                if (nlines[s] == 0) continue;
+                BStream& B = bt->st[s];
+                StreamDesc d{};
+                d.x = lines[s];
+                d.out = B.scores;
+                d.outn = c.normalise ? B.scores_n : nullptr;
+                d.state = B.state;
+                d.t0 = B.t;
+                d.alpha = B.alpha;
+                d.eps = c.ridge;
+                d.p = B.p;
+                d.b = B.b;
+                d.n = nlines[s];
+                hd[nsd++] = d;
+                vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)lines[s] % (4 * esz)) == 0;
+                pmax = std::max(pmax, B.p);
+                B.t += nlines[s];
+            }
+            if (nsd > 0) {
+                Pass P{};
+                P.sd = g.d_sd[slot];
+                P.nstreams = nsd;
+                P.pmax = pmax;
+                P.vec4 = vec4;
+                HIPCHK(hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
+                                      bt->stream));
+                HIPCHK(launch_small(c.dtype, P, c.normalise, bt->ctr, bt->stream));
+            }
+            HIPCHK(hipEventRecord(g.slot_ev[slot], bt->stream));
+            continue;
+        }
         std::vector<int> off(g.streams.size(), 0);
         for (;;) {
             // streams with lines left, longest work first
@@ -308,7 +356,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
                 L += kl;
                 S += (kl + seg - 1) / seg;
                 pmax = std::max(pmax, B.p);
-                vec4 = vec4 && (B.b % 4 == 0);
+                vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)d.x % (4 * esz)) == 0;
                 taken.push_back({k, kl});
             }
             Pass P{};

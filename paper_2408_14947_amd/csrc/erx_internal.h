@@ -56,6 +56,9 @@ hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double*
                        unsigned long long* ctr, hipStream_t s);
 hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s);
 hipError_t launch_normalise(const Pass& P, hipStream_t s);
+// fused path for streams with at most 16 bands: one workgroup per stream, its
+// n lines in order, state read from and written back to StreamDesc::state
+hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s);
 hipError_t launch_labels(const float* dn, int n, int p, float tau, long long t0, int warmup,
                          unsigned char* out, hipStream_t s);
 

@@ -144,3 +144,85 @@ def test_batch_uneven_u16(erx):
         err = rel_err(o.cpu().numpy(), want).max()
         log(f"  b={sc.bands} p={sc.pixels}: max err {err:.2e}")
         assert err <= TOL
+
+
+def small_specs(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        b = int(rng.integers(1, 17))
+        p = int(rng.choice([2, 17, 96, 300, 1280]))
+        T = int(rng.integers(1, 70))
+        a = float(rng.choice([1.0, 0.3, 0.05]))
+        out.append((b, p, T, a))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u16"])
+def test_small_band_fused_path_matches_oracle(erx, storage):
+    """Streams of 1..16 bands through the fused one-workgroup-per-stream path,
+    pushed in two uneven parts, against the FP64 oracle; state after the pushes."""
+    specs = small_specs(40, {"f32": 1, "f16": 2, "u16": 3}[storage])
+    log(f"fused small-band path, {storage}, {len(specs)} streams")
+    data = []
+    for i, (b, p, T, a) in enumerate(specs):
+        sc = datagen.make_scene(51, i, b, p, T, kind="gauss", storage=storage, momentum=a)
+        data.append(datagen.lines(sc, 0, T)[0])
+    bt = erx.Batch([s[0] for s in specs], [s[1] for s in specs], [s[3] for s in specs], dtype=storage,
+                   small_path=1)
+    dev = [x.cuda() for x in data]
+    cut = [T // 3 for (_, _, T, _) in specs]
+    oras = [oracle.Stream(b, p, a, 1e-5) for (b, p, T, a) in specs]
+    for part in range(2):
+        chunk = [x[:k] if part == 0 else x[k:] for x, k in zip(dev, cut)]
+        bt.push([c if c.shape[0] else None for c in chunk])
+        outs = bt.scores()
+        for s, (b, p, T, a) in enumerate(specs):
+            lo, hi = (0, cut[s]) if part == 0 else (cut[s], T)
+            if hi == lo:
+                assert outs[s] is None
+                continue
+            want = oras[s].push(datagen.storage_to_float64(data[s][lo:hi], storage))["delta"]
+            err = rel_err(outs[s].cpu().numpy(), want).max()
+            assert err <= TOL, (part, s, b, p, err)
+    for s, (b, p, T, a) in enumerate(specs):
+        t, mu, K = bt.state(s)
+        t_o, mu_o, K_o = oras[s].state()
+        assert t == T == t_o
+        np.testing.assert_allclose(mu, mu_o, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(K, K_o, rtol=1e-4, atol=1e-6 * max(1.0, np.abs(K_o).max()))
+    assert bt.stats()["fp64_refactors"] == sum(s[2] for s in specs)
+
+
+def test_small_band_fused_path_equals_general_path(erx):
+    specs = [(b, 640, 50, 0.1) for b in (3, 8, 12, 16)] * 3
+    data = []
+    for i, (b, p, T, a) in enumerate(specs):
+        sc = datagen.make_scene(52, i, b, p, T, kind="gauss", momentum=a)
+        data.append(datagen.lines(sc, 0, T)[0].cuda())
+    res = {}
+    for mode in (0, 1):
+        bt = erx.Batch([s[0] for s in specs], [s[1] for s in specs], [s[3] for s in specs], small_path=mode)
+        bt.push(data)
+        res[mode] = [o.cpu().numpy().astype(np.float64) for o in bt.scores()]
+    for a, b in zip(res[0], res[1]):
+        assert rel_err(b, a).max() <= 2 * TOL
+
+
+def test_small_band_fused_path_not_pd(erx):
+    """Ridge 0 and a constant band: every line's covariance is singular; the
+    fused path flags the same lines as the oracle and scores them NaN."""
+    b, p, T = 6, 64, 5
+    rng = np.random.default_rng(7)
+    X = rng.normal(0.5, 0.1, size=(T, p, b)).astype(np.float32)
+    X[:, :, 2] = 0.25
+    bt = erx.Batch([b] * 33, [p] * 33, [0.2] * 33, ridge=0.0, small_path=1)
+    dev = torch.from_numpy(X).cuda()
+    bt.push([dev] * 33)
+    with pytest.raises(erx.ErxError):
+        bt.scores(allow_notpd=False)
+    outs = bt.scores()
+    want = oracle.run(X, 0.2, 0.0)
+    assert np.all(want["notpd"])
+    assert np.all(np.isnan(outs[0].cpu().numpy()))
+    assert bt.stats()["notpd"] == 33 * T

@@ -344,3 +344,21 @@ def test_long_scan_224_full_size_sampled(erx):
     log(f"  stats {st}")
     del X
     torch.cuda.empty_cache()
+
+
+def test_unaligned_device_buffer(erx):
+    """A device buffer that is element- but not 16-byte aligned (b % 4 == 0)
+    takes the element-load path and matches the oracle."""
+    b, p, T = 8, 97, 12
+    log("unaligned device buffer")
+    sc = datagen.make_scene(33, 0, b, p, T)
+    X, _ = datagen.lines(sc, 0, T)
+    flat = torch.empty(T * p * b + 1, dtype=torch.float32, device="cuda")
+    Xd = flat[1:].view(T, p, b)
+    Xd.copy_(X.cuda())
+    assert Xd.data_ptr() % 16 != 0
+    det = erx.Detector(b, p, 0.1, block_lines=5, scan_lines=2)
+    det.push(Xd)
+    got = det.scores().cpu().numpy()
+    want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
+    assert rel_err(got, want).max() <= TOL
