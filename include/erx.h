@@ -193,6 +193,60 @@ ERX_API int erx_batch_small_path(erx_batch *bt, int mode);
 ERX_API int erx_batch_synchronize(erx_batch *bt);
 ERX_API void erx_batch_destroy(erx_batch *bt);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned band-projection surrogate (a stated change to the method, the learned analogue of
+ * the sparse random projection of Sec. III-B).  For b-band FP32 lines:
+ *     z = W x + c (ERX_SURR_K outputs),  u = L_z^{-1} (z - mu_z) with (mu_z, L_z) the ERX
+ *     statistics of the z stream (same momentum, first-line initialisation, ridge 1e-5),
+ *     o = w2 . relu(A1 u + a1) + c2 (ERX_SURR_HIDDEN hidden units),  score = ||u|| exp(o).
+ * Parameters are one flat FP32 vector (the master copy; the projection uses an FP16 copy of
+ * W refreshed at every change), laid out as W [K][b] row-major, c [K], A1 [HIDDEN][K]
+ * row-major, a1 [HIDDEN], w2 [HIDDEN], c2: erx_surrogate_num_params() floats.
+ * A handle owns its device memory and its own stream; calls block until done.
+ * --------------------------------------------------------------------------------------- */
+#define ERX_SURR_K 16
+#define ERX_SURR_HIDDEN 64
+typedef struct erx_surr erx_surr;
+/* NULL on error (bands outside [1, ERX_MAX_BANDS], no memory).  seed: initial parameters. */
+ERX_API erx_surr *erx_surrogate_create(int bands, unsigned long long seed);
+ERX_API int erx_surrogate_num_params(const erx_surr *net);
+/* host arrays of erx_surrogate_num_params() floats; set also resets the Adam moments */
+ERX_API int erx_surrogate_set_params(erx_surr *net, const float *params);
+ERX_API int erx_surrogate_get_params(const erx_surr *net, float *params);
+/* Surrogate scores of n lines [n][pixels][bands] (device FP32) of a stream scored from its
+ * first line into out [n][pixels] (device FP32). */
+ERX_API int erx_surrogate_scores(erx_surr *net, const float *lines, int n, int pixels, float momentum,
+                                 float *out);
+/* One training step on n consecutive lines (device FP32 [n][pixels][bands]) of a stream
+ * scored from its first line, against targets [n][pixels] (device FP32, the plain-ERX
+ * scores of the same lines): loss = mean (log score - log target)^2 with the z-stream
+ * statistics held fixed; the gradient is kept (erx_surrogate_grads) and, for lr > 0, one
+ * Adam step (beta 0.9 / 0.999, eps 1e-8) is taken.  *loss receives the loss before the step. */
+ERX_API int erx_surrogate_train_step(erx_surr *net, const float *lines, const float *targets, int n,
+                                     int pixels, float momentum, float lr, float *loss);
+/* gradient of the last training step, host array of erx_surrogate_num_params() floats */
+ERX_API int erx_surrogate_grads(const erx_surr *net, float *grads);
+ERX_API void erx_surrogate_destroy(erx_surr *net);
+
+/* A stream scored by the surrogate and checked against plain ERX: line t with (t+1) %
+ * check_every == 0 is also scored by plain ERX and by the surrogate, each on a state that
+ * sees only those lines (momentum 1 - (1 - momentum)^check_every); the drift of a check is
+ * the median over the line's pixels of |log surrogate - log plain| of those two scores.  After two consecutive checks with drift
+ * above drift_threshold the stream switches to plain ERX (re-initialised from the next line)
+ * for good.  The detector keeps a pointer to net, which must outlive it. */
+typedef struct erx_sdet erx_sdet;
+ERX_API erx_sdet *erx_surrogate_detector_create(erx_surr *net, int pixels, float momentum,
+                                                float drift_threshold, int check_every);
+/* lines: device FP32 [n][pixels][bands]; blocks at every check line */
+ERX_API int erx_surrogate_detector_push(erx_sdet *sd, const float *lines, int n);
+/* out: n_last * pixels floats, host or device */
+ERX_API int erx_surrogate_detector_scores(erx_sdet *sd, float *out);
+/* active: 1 while the surrogate scores; checks / drifts: counts; switched_at: first line
+ * scored by plain ERX after the switch, or -1 */
+ERX_API int erx_surrogate_detector_status(const erx_sdet *sd, int *active, long long *checks,
+                                          long long *drifts, long long *switched_at);
+ERX_API void erx_surrogate_detector_destroy(erx_sdet *sd);
+
 /* Wait for all work enqueued on the handle's stream. */
 ERX_API int erx_synchronize(erx_ctx *h);
 

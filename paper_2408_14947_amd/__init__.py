@@ -30,7 +30,13 @@ EXPORTS = (
     "erx_profile_read", "erx_batch_create", "erx_batch_set_stream", "erx_batch_push",
     "erx_batch_scores", "erx_batch_get_state", "erx_batch_stats", "erx_batch_use_graphs", "erx_batch_small_path",
     "erx_batch_synchronize", "erx_batch_destroy", "erx_synchronize", "erx_destroy", "erx_last_error",
+    "erx_surrogate_create", "erx_surrogate_num_params", "erx_surrogate_set_params",
+    "erx_surrogate_get_params", "erx_surrogate_scores", "erx_surrogate_train_step",
+    "erx_surrogate_grads", "erx_surrogate_destroy", "erx_surrogate_detector_create",
+    "erx_surrogate_detector_push", "erx_surrogate_detector_scores", "erx_surrogate_detector_status",
+    "erx_surrogate_detector_destroy",
 )
+SURR_K, SURR_HIDDEN = 16, 64
 
 
 class ErxError(RuntimeError):
@@ -98,6 +104,20 @@ def load(path: str = LIB_PATH):
         "erx_synchronize": (ip, [vp]),
         "erx_destroy": (None, [vp]),
         "erx_last_error": (C.c_char_p, []),
+        "erx_surrogate_create": (vp, [ip, C.c_ulonglong]),
+        "erx_surrogate_num_params": (ip, [vp]),
+        "erx_surrogate_set_params": (ip, [vp, vp]),
+        "erx_surrogate_get_params": (ip, [vp, vp]),
+        "erx_surrogate_scores": (ip, [vp, vp, ip, ip, C.c_float, vp]),
+        "erx_surrogate_train_step": (ip, [vp, vp, vp, ip, ip, C.c_float, C.c_float, C.POINTER(C.c_float)]),
+        "erx_surrogate_grads": (ip, [vp, vp]),
+        "erx_surrogate_destroy": (None, [vp]),
+        "erx_surrogate_detector_create": (vp, [vp, ip, C.c_float, C.c_float, ip]),
+        "erx_surrogate_detector_push": (ip, [vp, vp, ip]),
+        "erx_surrogate_detector_scores": (ip, [vp, vp]),
+        "erx_surrogate_detector_status": (ip, [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong),
+                                                C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+        "erx_surrogate_detector_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -378,3 +398,128 @@ class Batch:
 
 __all__ = ["Detector", "Batch", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
            "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "MAX_BANDS"]
+
+
+# ---------------------------------------------------------------------------
+# learned projection surrogate
+# ---------------------------------------------------------------------------
+PARAM_ORDER = ("W", "c", "A1", "a1", "w2", "c2")
+
+
+def _param_shapes(bands):
+    return {"W": (SURR_K, bands), "c": (SURR_K,), "A1": (SURR_HIDDEN, SURR_K), "a1": (SURR_HIDDEN,),
+            "w2": (SURR_HIDDEN,), "c2": (1,)}
+
+
+class Surrogate:
+    """Learned band projection + small network (a handle of the C library)."""
+
+    def __init__(self, bands: int, seed: int = 0):
+        lib = load()
+        self._lib = lib
+        self.bands = int(bands)
+        self._h = lib.erx_surrogate_create(self.bands, C.c_ulonglong(seed))
+        if not self._h:
+            raise ErxError(ERX_EINVAL, last_error())
+        self.nparams = lib.erx_surrogate_num_params(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.erx_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _unflat(self, flat):
+        out, k = {}, 0
+        for name in PARAM_ORDER:
+            shp = _param_shapes(self.bands)[name]
+            n = int(np.prod(shp))
+            out[name] = flat[k:k + n].reshape(shp).copy()
+            k += n
+        return out
+
+    def params(self) -> dict:
+        flat = np.empty(self.nparams, np.float32)
+        _check(self._lib.erx_surrogate_get_params(self._h, C.c_void_p(flat.ctypes.data)))
+        return self._unflat(flat)
+
+    def set_params(self, params: dict):
+        flat = np.concatenate([np.asarray(params[n], np.float32).reshape(-1) for n in PARAM_ORDER])
+        if flat.size != self.nparams:
+            raise ValueError("parameter sizes do not match the band count")
+        flat = np.ascontiguousarray(flat)
+        _check(self._lib.erx_surrogate_set_params(self._h, C.c_void_p(flat.ctypes.data)))
+
+    def grads(self) -> dict:
+        flat = np.empty(self.nparams, np.float32)
+        _check(self._lib.erx_surrogate_grads(self._h, C.c_void_p(flat.ctypes.data)))
+        return self._unflat(flat)
+
+    def scores(self, lines, momentum: float):
+        """Scores of lines [n, pixels, bands] (float32 CUDA tensor) of a stream from its first line."""
+        import torch
+        n, p, b = lines.shape
+        out = torch.empty((n, p), dtype=torch.float32, device=lines.device)
+        torch.cuda.synchronize()
+        _check(self._lib.erx_surrogate_scores(self._h, C.c_void_p(_ptr(lines)), n, p, C.c_float(momentum),
+                                              C.c_void_p(out.data_ptr())))
+        return out
+
+    def train_step(self, lines, targets, momentum: float, lr: float) -> float:
+        import torch
+        n, p, b = lines.shape
+        loss = C.c_float()
+        torch.cuda.synchronize()
+        _check(self._lib.erx_surrogate_train_step(self._h, C.c_void_p(_ptr(lines)), C.c_void_p(_ptr(targets)), n, p,
+                                                  C.c_float(momentum), C.c_float(lr), C.byref(loss)))
+        return float(loss.value)
+
+
+class SurrogateDetector:
+    """A stream scored by a Surrogate, checked against plain ERX every check_every lines."""
+
+    def __init__(self, net: Surrogate, pixels: int, momentum: float, drift_threshold: float = 0.05,
+                 check_every: int = 32):
+        self._lib = net._lib
+        self.net = net  # keeps the network alive
+        self.pixels = int(pixels)
+        self._h = self._lib.erx_surrogate_detector_create(net._h, self.pixels, C.c_float(momentum),
+                                                          C.c_float(drift_threshold), int(check_every))
+        if not self._h:
+            raise ErxError(ERX_EINVAL, last_error())
+        self.last_n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.erx_surrogate_detector_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, lines):
+        import torch
+        torch.cuda.synchronize()
+        _check(self._lib.erx_surrogate_detector_push(self._h, C.c_void_p(_ptr(lines)), int(lines.shape[0])))
+        self.last_n = int(lines.shape[0])
+        return self
+
+    def scores(self):
+        import torch
+        out = torch.empty((self.last_n, self.pixels), dtype=torch.float32, device="cuda")
+        _check(self._lib.erx_surrogate_detector_scores(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def status(self) -> dict:
+        a = C.c_int()
+        ch, dr, sw = C.c_longlong(), C.c_longlong(), C.c_longlong()
+        _check(self._lib.erx_surrogate_detector_status(self._h, C.byref(a), C.byref(ch), C.byref(dr), C.byref(sw)))
+        return {"active": bool(a.value), "checks": ch.value, "drifts": dr.value, "switched_at": sw.value}

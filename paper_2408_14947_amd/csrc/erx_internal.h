@@ -56,6 +56,8 @@ hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double*
                        unsigned long long* ctr, hipStream_t s);
 hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s);
 hipError_t launch_normalise(const Pass& P, hipStream_t s);
+// exact (FP64) statistics of one-tile FP32 streams, in the k_gram layout
+hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s);
 // fused path for streams with at most 16 bands: one workgroup per stream, its
 // n lines in order, state read from and written back to StreamDesc::state
 hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s);

@@ -1687,6 +1687,99 @@ hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const
     return hipGetLastError();
 }
 
+// ============================================================================
+// Exact statistics of one-tile FP32 streams (b <= 16) for the pass pipeline:
+// per line the mean and centred covariance (Eqs. (18)-(19)) with FP64
+// differences and FP64 MFMA products, written in the layout of k_gram4.  One
+// workgroup per line; each wave takes tiles w, w+4, ... with its own shift
+// (the first pixel of its first tile) and the wave sums are combined exactly.
+// Used for the projected stream of the learned surrogate, whose covariance can
+// be far less well conditioned than the data's.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_gram1x(const Pass P, double* __restrict__ stats, long long E)
+{
+    const int line = blockIdx.x;
+    if (line >= P.nlines) return;  // uniform for the workgroup
+    const StreamDesc d = stream_of_line(P, line);
+    const int p = d.p, b = d.b;
+    const float* X = (const float*)d.x + (size_t)(line - d.line0) * p * b;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    __shared__ double red_s[4][256 + 16];
+    __shared__ double wsh_s[4][16];
+    __shared__ int wn_s[4];
+    const int ntile = (p + 15) >> 4;
+    const int ntw = ntile > w ? (ntile - w + 3) >> 2 : 0;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    double bsd = 0.0, sh = 0.0;
+    for (int tt = w; tt < ntile; tt += 4) {
+        float xf[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = 16 * tt + 4 * g + i;
+            const bool ok = px < p && c < b;
+            const float v = glb(X)[ok ? (size_t)px * b + c : 0];
+            xf[i] = ok ? v : 0.f;
+        }
+        if (tt == w) sh = (double)__shfl(xf[0], c);
+        d4 xv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int px = 16 * tt + 4 * g + i;
+            xv[i] = (px < p && c < b) ? (double)xf[i] - sh : 0.0;
+        }
+        bsd += (xv[0] + xv[1]) + (xv[2] + xv[3]);
+        acc = mma_xty(acc, xv, xv);
+    }
+    bsd += __shfl_xor(bsd, 16);
+    bsd += __shfl_xor(bsd, 32);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red_s[w][(4 * i + g) * 16 + c] = acc[i];  // FP64 layout: row 4i+g
+    if (g == 0) {
+        red_s[w][256 + c] = bsd;
+        wsh_s[w][c] = ntw ? sh : 0.0;
+    }
+    if (lane == 0) wn_s[w] = ntw ? 16 * ntw - (((ntile - 1 - w) & 3) == 0 ? 16 * ntile - p : 0) : 0;
+    __syncthreads();
+    if (w != 0) return;
+    const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
+    double mw_c[4], m_c = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int nw = wn_s[v];
+        mw_c[v] = nw ? wsh_s[v][c] + red_s[v][256 + c] / nw : 0.0;
+        m_c += nw * mw_c[v];
+    }
+    m_c *= inv_p;
+    double* ls = stats + (size_t)line * E;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = 4 * g + i;
+        double cs = 0.0, m_r = 0.0, mw_r[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int nw = wn_s[v];
+            mw_r[v] = nw ? wsh_s[v][row] + red_s[v][256 + row] / nw : 0.0;
+            m_r += nw * mw_r[v];
+        }
+        m_r *= inv_p;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int nw = wn_s[v];
+            if (nw == 0) continue;
+            cs += red_s[v][row * 16 + c] - red_s[v][256 + row] * red_s[v][256 + c] / nw +
+                  nw * (mw_r[v] - m_r) * (mw_c[v] - m_c);
+        }
+        ls[lane * 4 + i] = cs * inv_p1;  // state layout: lane (g, c), register i = row 4g+i
+    }
+    if (g == 0) ls[256 + c] = (c < b) ? m_c : 0.0;
+}
+
+hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gram1x, dim3((unsigned)P.nlines), dim3(256), 0, s, P, stats, stat_entries(1));
+    return hipGetLastError();
+}
+
 hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s)
 {
     const dim3 grid((unsigned)P.nstreams), block(256);

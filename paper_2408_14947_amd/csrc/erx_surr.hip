@@ -1,0 +1,767 @@
+// Learned band-projection surrogate of ERX: kernels and C-ABI front end.
+//
+// A stated change to the method, the learned analogue of the sparse random
+// projection of Sec. III-B.  For a stream of b-band lines:
+//     z     = W x + c                     (16 outputs; W held in FP16 for the
+//                                          projection, FP32 master copy)
+//     u     = L_z^{-1} (z - mu_z)          ERX (Sec. III-C/D) on the z stream
+//     o     = w2 . relu(A1 u + a1) + c2    (16 -> 64 -> 1)
+//     score = ||u|| exp(o)
+// Training minimises mean (log score - log target)^2 over the pixels of a
+// batch of consecutive lines of a stream (scored from its first line), the
+// targets being plain-ERX scores; mu_z and L_z are held fixed in the gradient.
+// Adam with FP32 master weights; the FP16 copy of W is refreshed every step.
+//
+// The surrogate detector scores a stream with the surrogate and checks it:
+// every R-th line is scored twice more, by plain ERX and by the surrogate, both
+// on backgrounds that see only the check lines (momentum 1 - (1 - alpha)^R),
+// so that the comparison measures the projection and the network and not the
+// difference between a check-line background and the full one; when the median
+// over the line's pixels of |log surrogate - log plain| exceeds theta on two
+// consecutive checks, the stream switches to plain ERX, re-initialised from
+// the next line.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/erx.h"
+#include "erx_internal.h"
+#include "erx_runtime.h"
+
+using namespace erx;
+
+#define fail erx::set_error
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(ERX_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+constexpr int SK = ERX_SURR_K;       // projection width
+constexpr int SH = ERX_SURR_HIDDEN;  // hidden units
+constexpr int SEG = 64;              // scan segment of the projected stream
+constexpr double SURR_RIDGE = 1e-5;  // ridge of the projected stream
+
+struct Off {
+    int W, c, A1, a1, w2, c2, n;
+};
+__host__ __device__ inline Off offsets(int b)
+{
+    Off o;
+    o.W = 0;
+    o.c = SK * b;
+    o.A1 = o.c + SK;
+    o.a1 = o.A1 + SH * SK;
+    o.w2 = o.a1 + SH;
+    o.c2 = o.w2 + SH;
+    o.n = o.c2 + 1;
+    return o;
+}
+
+// ---------------------------------------------------------------- kernels
+// z = W x + c - zref, one thread per pixel, accumulated in FP64; W (FP16)
+// transposed in LDS so that every lane reads the same words (broadcast).
+// zref is a per-stream constant (the projection of the stream's first pixel):
+// ERX is exactly invariant to a constant shift of its input, and storing the
+// shifted projection in FP32 keeps its rounding small relative to the spread
+// of the data, which is what the statistics of the z stream resolve.
+__global__ __launch_bounds__(256) void k_sproj(const float* __restrict__ X, long long npx, int b,
+                                               const __half* __restrict__ W16, const float* __restrict__ P,
+                                               int offc, const double* __restrict__ zref, float* __restrict__ Z)
+{
+    extern __shared__ float Ws[];  // [b][16]
+    for (int i = threadIdx.x; i < SK * b; i += 256) {
+        const int o = i / b, k = i - o * b;
+        Ws[k * SK + o] = __half2float(W16[i]);
+    }
+    __syncthreads();
+    const long long px = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (px >= npx) return;  // no barrier follows
+    double z[SK];
+#pragma unroll
+    for (int o = 0; o < SK; ++o) z[o] = (double)P[offc + o] - zref[o];
+    const float* xr = X + px * b;
+    for (int k = 0; k < b; ++k) {
+        const double xk = (double)xr[k];
+        const float4* wk = (const float4*)&Ws[k * SK];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 w = wk[q];
+            z[4 * q + 0] += (double)w.x * xk;
+            z[4 * q + 1] += (double)w.y * xk;
+            z[4 * q + 2] += (double)w.z * xk;
+            z[4 * q + 3] += (double)w.w * xk;
+        }
+    }
+    float4* zo = (float4*)(Z + px * SK);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        zo[q] = make_float4((float)z[4 * q], (float)z[4 * q + 1], (float)z[4 * q + 2], (float)z[4 * q + 3]);
+}
+
+// zref = W x0 + c for one pixel x0 (FP64), one thread per output
+__global__ __launch_bounds__(64) void k_zref(const float* __restrict__ x0, int b, const __half* __restrict__ W16,
+                                             const float* __restrict__ P, int offc, double* __restrict__ zref)
+{
+    const int o = threadIdx.x;
+    if (o >= SK) return;
+    double s = (double)P[offc + o];
+    for (int k = 0; k < b; ++k) s += (double)__half2float(W16[o * b + k]) * (double)x0[k];
+    zref[o] = s;
+}
+
+// Per pixel: u = M (z - mu), the network, the score; with TRAIN also the loss
+// term, d loss / d log score (G), the hidden pre-activations, u and
+// d loss / dz, for the reduction kernel.  One workgroup per (line, 256
+// pixels); M (from the transposed accumulator-layout tile of the ERX pass), mu
+// and the network in LDS.
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, int p, int ngrp,
+                                                  const float* __restrict__ Mt, const float* __restrict__ mu32,
+                                                  const float* __restrict__ P, int offA1, int offa1, int offw2,
+                                                  int offc2, float* __restrict__ out, const float* __restrict__ target,
+                                                  float* __restrict__ U, float* __restrict__ Pre,
+                                                  float* __restrict__ G, float* __restrict__ dZ,
+                                                  float* __restrict__ loss, float inv_n)
+{
+    __shared__ float Ms[SK * SK];  // M[r][q]
+    __shared__ float A1s[SH * SK];
+    __shared__ float a1s[SH], w2s[SH], mus[SK];
+    __shared__ float red[4];
+    const int line = blockIdx.x / ngrp, grp = blockIdx.x - line * ngrp;
+    const int tid = threadIdx.x;
+    {
+        const int r = tid >> 4, q = tid & 15;  // Mt holds M^T: element (r, q) of M at lane 16(q/4)+r, reg q%4
+        Ms[r * SK + q] = Mt[(size_t)line * 256 + (16 * (q >> 2) + r) * 4 + (q & 3)];
+    }
+    for (int i = tid; i < SH * SK; i += 256) A1s[i] = P[offA1 + i];
+    if (tid < SH) {
+        a1s[tid] = P[offa1 + tid];
+        w2s[tid] = P[offw2 + tid];
+    }
+    if (tid < SK) mus[tid] = mu32[(size_t)line * SK + tid];
+    const float c2 = P[offc2];
+    __syncthreads();
+    const int px = grp * 256 + tid;
+    const bool ok = px < p;
+    const size_t idx = (size_t)line * p + (ok ? px : 0);
+    float r[SK], u[SK];
+    const float* zr = Z + idx * SK;
+#pragma unroll
+    for (int q = 0; q < SK; ++q) r[q] = zr[q] - mus[q];
+    float nu2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < SK; ++i) {
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < SK; ++q) s += Ms[i * SK + q] * r[q];
+        u[i] = s;
+        nu2 += s * s;
+    }
+    float o = c2;
+    float pre[TRAIN ? SH : 1];
+#pragma unroll
+    for (int j = 0; j < SH; ++j) {
+        float s = a1s[j];
+#pragma unroll
+        for (int i = 0; i < SK; ++i) s += A1s[j * SK + i] * u[i];
+        if (TRAIN) pre[j] = s;
+        o += w2s[j] * fmaxf(s, 0.f);
+    }
+    if (!TRAIN) {
+        if (ok) out[idx] = sqrtf(nu2) * expf(o);
+        return;
+    }
+    const float e = ok ? 0.5f * logf(nu2) + o - logf(target[idx]) : 0.f;
+    const float g = 2.f * e * inv_n;
+    float dU[SK];
+#pragma unroll
+    for (int i = 0; i < SK; ++i) dU[i] = g * u[i] / nu2;
+#pragma unroll
+    for (int j = 0; j < SH; ++j) {
+        const float dp = pre[j] > 0.f ? g * w2s[j] : 0.f;
+#pragma unroll
+        for (int i = 0; i < SK; ++i) dU[i] += dp * A1s[j * SK + i];
+    }
+    if (ok) {
+        G[idx] = g;
+        float* ur = U + idx * SK;
+        float* dz = dZ + idx * SK;
+#pragma unroll
+        for (int i = 0; i < SK; ++i) ur[i] = u[i];
+#pragma unroll
+        for (int q = 0; q < SK; ++q) {  // dz = M^T du
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < SK; ++i) s += dU[i] * Ms[i * SK + q];
+            dz[q] = s;
+        }
+        float* pr = Pre + idx * SH;
+#pragma unroll
+        for (int j = 0; j < SH; ++j) pr[j] = pre[j];
+    }
+    // loss: wave sums, then one atomic per workgroup
+    float e2 = e * e * inv_n;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) e2 += __shfl_xor(e2, m);
+    if ((tid & 63) == 0) red[tid >> 6] = e2;
+    __syncthreads();
+    if (tid == 0) atomicAdd(loss, (red[0] + red[1]) + (red[2] + red[3]));
+}
+
+// Gradient sums over a chunk of pixels, one thread per parameter entry (the
+// parameter layout: W [16][b], c [16], A1 [64][16], a1 [64], w2 [64], c2).
+__global__ __launch_bounds__(256) void k_surr_reduce(const float* __restrict__ X, int b, long long npx, int chunk,
+                                                     const float* __restrict__ U, const float* __restrict__ Pre,
+                                                     const float* __restrict__ G, const float* __restrict__ dZ,
+                                                     const float* __restrict__ P, float* __restrict__ grad)
+{
+    const Off off = offsets(b);
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= off.n) return;
+    const long long p0 = (long long)blockIdx.y * chunk;
+    const long long p1 = std::min<long long>(npx, p0 + chunk);
+    float s = 0.f;
+    if (e < off.c) {  // dW[o][k] = sum dz_o x_k
+        const int o = e / b, k = e - o * b;
+        for (long long px = p0; px < p1; ++px) s += dZ[px * SK + o] * X[px * b + k];
+    } else if (e < off.A1) {  // dc = sum dz
+        const int o = e - off.c;
+        for (long long px = p0; px < p1; ++px) s += dZ[px * SK + o];
+    } else if (e < off.a1) {  // dA1[j][i] = sum [pre_j > 0] g w2_j u_i
+        const int j = (e - off.A1) / SK, i = (e - off.A1) % SK;
+        const float w2j = P[off.w2 + j];
+        for (long long px = p0; px < p1; ++px)
+            s += Pre[px * SH + j] > 0.f ? G[px] * w2j * U[px * SK + i] : 0.f;
+    } else if (e < off.w2) {  // da1[j] = sum [pre_j > 0] g w2_j
+        const int j = e - off.a1;
+        const float w2j = P[off.w2 + j];
+        for (long long px = p0; px < p1; ++px) s += Pre[px * SH + j] > 0.f ? G[px] * w2j : 0.f;
+    } else if (e < off.c2) {  // dw2[j] = sum g relu(pre_j)
+        const int j = e - off.w2;
+        for (long long px = p0; px < p1; ++px) s += G[px] * fmaxf(Pre[px * SH + j], 0.f);
+    } else {  // dc2 = sum g
+        for (long long px = p0; px < p1; ++px) s += G[px];
+    }
+    atomicAdd(&grad[e], s);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float* __restrict__ grad,
+                                              float* __restrict__ m, float* __restrict__ v, __half* __restrict__ W16,
+                                              int n, int nW, float lr, float b1, float b2, float eps, float c1,
+                                              float c2)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float g = grad[e];
+    const float mm = b1 * m[e] + (1.f - b1) * g;
+    const float vv = b2 * v[e] + (1.f - b2) * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    const float w = P[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    P[e] = w;
+    if (e < nW) W16[e] = __float2half(w);
+}
+
+__global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ P, __half* __restrict__ W16, int n)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < n) W16[e] = __float2half(P[e]);
+}
+
+// ERX workspace of a projected (16-band) stream
+struct Erx16 {
+    long long cap = 0;  // lines
+    int capp = 0;       // pixels
+    float* Z = nullptr;
+    double* stats = nullptr;
+    double* carry = nullptr;
+    float* Mt = nullptr;
+    float* mu32 = nullptr;
+    int* flags = nullptr;
+    float* cond = nullptr;
+    double* state = nullptr;
+    double* zref = nullptr;
+    unsigned long long* ctr = nullptr;
+    void release()
+    {
+        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond, state, zref, ctr};
+        for (void* q : d)
+            if (q) (void)hipFree(q);
+        *this = Erx16();
+    }
+    hipError_t ensure(long long n, int p)
+    {
+        if (!state) {
+            if (hipMalloc(&state, stat_entries(1) * sizeof(double)) != hipSuccess ||
+                hipMalloc(&zref, SK * sizeof(double)) != hipSuccess ||
+                hipMalloc(&ctr, 4 * sizeof(unsigned long long)) != hipSuccess ||
+                hipMemset(state, 0, stat_entries(1) * sizeof(double)) != hipSuccess ||
+                hipMemset(ctr, 0, 4 * sizeof(unsigned long long)) != hipSuccess)
+                return hipErrorOutOfMemory;
+        }
+        if (n <= cap && p <= capp) return hipSuccess;
+        const long long N = std::max(n, cap);
+        const int Pp = std::max(p, capp);
+        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond};
+        for (void* q : d)
+            if (q) (void)hipFree(q);
+        Z = nullptr;
+        stats = carry = nullptr;
+        Mt = mu32 = cond = nullptr;
+        flags = nullptr;
+        const long long E = stat_entries(1);
+        const long long nseg = (N + SEG - 1) / SEG + 2;
+        if (hipMalloc(&Z, (size_t)N * Pp * SK * sizeof(float)) != hipSuccess ||
+            hipMalloc(&stats, (size_t)N * E * sizeof(double)) != hipSuccess ||
+            hipMalloc(&carry, (size_t)nseg * E * sizeof(double)) != hipSuccess ||
+            hipMalloc(&Mt, (size_t)N * 256 * sizeof(float)) != hipSuccess ||
+            hipMalloc(&mu32, (size_t)N * SK * sizeof(float)) != hipSuccess ||
+            hipMalloc(&flags, (size_t)N * sizeof(int)) != hipSuccess ||
+            hipMalloc(&cond, (size_t)N * sizeof(float)) != hipSuccess)
+            return hipErrorOutOfMemory;
+        cap = N;
+        capp = Pp;
+        return hipSuccess;
+    }
+    // statistics and inverse factors of the n projected lines in Z (state carried)
+    hipError_t pass(hipStream_t s, int n, int p, double alpha, long long t0, float* dummy_out)
+    {
+        Pass P{};
+        P.sd = nullptr;
+        P.one.x = Z;
+        P.one.out = dummy_out;
+        P.one.outn = nullptr;
+        P.one.state = state;
+        P.one.t0 = t0;
+        P.one.alpha = alpha;
+        P.one.eps = SURR_RIDGE;
+        P.one.p = p;
+        P.one.b = SK;
+        P.one.n = n;
+        P.nstreams = 1;
+        P.nlines = n;
+        P.nseg = (n + SEG - 1) / SEG;
+        P.seg = SEG;
+        P.pmax = p;
+        P.vec4 = 1;
+        hipError_t e;
+        if ((e = launch_gram1x(P, stats, s)) != hipSuccess) return e;
+        if ((e = launch_scan_local(P, 1, stats, s)) != hipSuccess) return e;
+        if ((e = launch_scan_carry(P, 1, stats, carry, s)) != hipSuccess) return e;
+        return launch_chol(1, 1, P, 1, stats, carry, Mt, mu32, flags, cond, 0.0, 0, ctr, s);
+    }
+};
+
+bool is_device(const void* ptr)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct erx_surr {
+    int b = 0;
+    Off off{};
+    float* P = nullptr;
+    float* grad = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    __half* W16 = nullptr;
+    float* loss = nullptr;
+    long long step = 0;
+    hipStream_t stream = nullptr;
+    Erx16 erx;
+    // training workspace
+    long long capN = 0;
+    float* U = nullptr;
+    float* Pre = nullptr;
+    float* G = nullptr;
+    float* dZ = nullptr;
+    float* dummy = nullptr;
+};
+
+struct erx_sdet {
+    erx_surr* net = nullptr;
+    int p = 0;
+    float alpha = 0.f, theta = 0.f;
+    int R = 0;
+    long long t = 0;
+    bool active = true;
+    int drift_run = 0;
+    long long checks = 0, drifts = 0, switched_at = -1;
+    erx_ctx* monitor = nullptr;  // plain ERX on the check lines
+    erx_ctx* plain = nullptr;
+    hipStream_t stream = nullptr;
+    Erx16 erx;                   // the surrogate's projected stream
+    Erx16 mon16;                 // the surrogate on the check lines
+    float* mscore = nullptr;
+    float alpha_r = 0.f;
+    float* scores = nullptr;
+    long long cap = 0;
+    int last_n = 0;
+    float* dummy = nullptr;
+    std::vector<float> hs, hp;
+};
+
+namespace {
+
+// projection of n lines into erx.Z; at the first line of a stream (t0 == 0)
+// the stream's reference zref is set from its first pixel
+hipError_t project(erx_surr* net, hipStream_t s, Erx16& erx, const float* X, long long npx, long long t0)
+{
+    if (t0 == 0) hipLaunchKernelGGL(k_zref, dim3(1), dim3(64), 0, s, X, net->b, net->W16, net->P, net->off.c, erx.zref);
+    hipLaunchKernelGGL(k_sproj, dim3((unsigned)((npx + 255) / 256)), dim3(256), SK * net->b * sizeof(float), s, X,
+                       npx, net->b, net->W16, net->P, net->off.c, erx.zref, erx.Z);
+    return hipGetLastError();
+}
+
+hipError_t net_forward(erx_surr* net, hipStream_t s, Erx16& erx, const float* X, int n, int p, double alpha,
+                       long long t0, float* out, float* dummy)
+{
+    const long long npx = (long long)n * p;
+    hipError_t e = project(net, s, erx, X, npx, t0);
+    if (e != hipSuccess) return e;
+    if ((e = erx.pass(s, n, p, alpha, t0, dummy)) != hipSuccess) return e;
+    const int ngrp = (p + 255) / 256;
+    hipLaunchKernelGGL((k_surr_pix<false>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, erx.Z, p, ngrp,
+                       erx.Mt, erx.mu32, net->P, net->off.A1, net->off.a1, net->off.w2, net->off.c2, out, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, 0.f);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+erx_surr* erx_surrogate_create(int bands, unsigned long long seed)
+{
+    if (bands < 1 || bands > ERX_MAX_BANDS) {
+        fail(ERX_EINVAL, "erx_surrogate_create: bands must be in [1, %d]", ERX_MAX_BANDS);
+        return nullptr;
+    }
+    erx_surr* net = new (std::nothrow) erx_surr();
+    if (!net) {
+        fail(ERX_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    net->b = bands;
+    net->off = offsets(bands);
+    const int n = net->off.n;
+    // initialisation: W ~ N(0, 1/b), A1 ~ N(0, 1/16), w2 ~ N(0, 0.01^2), biases 0
+    std::vector<float> h(n, 0.f);
+    unsigned long long st = seed * 0x9E3779B97F4A7C15ull + 1;
+    auto unif = [&]() {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        return ((st >> 11) + 0.5) / 9007199254740992.0;
+    };
+    auto normal = [&]() { return std::sqrt(-2.0 * std::log(unif())) * std::cos(6.283185307179586 * unif()); };
+    for (int i = 0; i < SK * bands; ++i) h[net->off.W + i] = (float)(normal() / std::sqrt((double)bands));
+    for (int i = 0; i < SH * SK; ++i) h[net->off.A1 + i] = (float)(normal() / std::sqrt((double)SK));
+    for (int i = 0; i < SH; ++i) h[net->off.w2 + i] = (float)(0.01 * normal());
+    bool ok = hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc(&net->P, n * sizeof(float)) == hipSuccess &&
+              hipMalloc(&net->grad, n * sizeof(float)) == hipSuccess &&
+              hipMalloc(&net->m, n * sizeof(float)) == hipSuccess && hipMalloc(&net->v, n * sizeof(float)) == hipSuccess &&
+              hipMalloc(&net->W16, SK * bands * sizeof(__half)) == hipSuccess &&
+              hipMalloc(&net->loss, sizeof(float)) == hipSuccess &&
+              hipMemcpy(net->P, h.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(net->grad, 0, n * sizeof(float)) == hipSuccess &&
+              hipMemset(net->m, 0, n * sizeof(float)) == hipSuccess &&
+              hipMemset(net->v, 0, n * sizeof(float)) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(k_to_half, dim3((SK * bands + 255) / 256), dim3(256), 0, net->stream, net->P, net->W16,
+                           SK * bands);
+        ok = hipStreamSynchronize(net->stream) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        erx_surrogate_destroy(net);
+        fail(ERX_ENOMEM, "erx_surrogate_create: device allocation failed");
+        return nullptr;
+    }
+    return net;
+}
+
+void erx_surrogate_destroy(erx_surr* net)
+{
+    if (!net) return;
+    if (net->stream) (void)hipStreamSynchronize(net->stream);
+    void* d[] = {net->P, net->grad, net->m, net->v, net->W16, net->loss, net->U, net->Pre, net->G, net->dZ, net->dummy};
+    for (void* q : d)
+        if (q) (void)hipFree(q);
+    net->erx.release();
+    if (net->stream) (void)hipStreamDestroy(net->stream);
+    delete net;
+}
+
+int erx_surrogate_num_params(const erx_surr* net)
+{
+    if (!net) return fail(ERX_EINVAL, "NULL surrogate");
+    return net->off.n;
+}
+
+int erx_surrogate_set_params(erx_surr* net, const float* params)
+{
+    if (!net || !params) return fail(ERX_EINVAL, "NULL argument");
+    HIPCHK(hipMemcpyAsync(net->P, params, net->off.n * sizeof(float), hipMemcpyHostToDevice, net->stream));
+    HIPCHK(hipMemsetAsync(net->m, 0, net->off.n * sizeof(float), net->stream));
+    HIPCHK(hipMemsetAsync(net->v, 0, net->off.n * sizeof(float), net->stream));
+    hipLaunchKernelGGL(k_to_half, dim3((SK * net->b + 255) / 256), dim3(256), 0, net->stream, net->P, net->W16,
+                       SK * net->b);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(net->stream));
+    net->step = 0;
+    return ERX_OK;
+}
+
+int erx_surrogate_get_params(const erx_surr* net, float* params)
+{
+    if (!net || !params) return fail(ERX_EINVAL, "NULL argument");
+    HIPCHK(hipMemcpyAsync(params, net->P, net->off.n * sizeof(float), hipMemcpyDeviceToHost, net->stream));
+    HIPCHK(hipStreamSynchronize(net->stream));
+    return ERX_OK;
+}
+
+int erx_surrogate_scores(erx_surr* net, const float* lines, int n, int pixels, float momentum, float* out)
+{
+    if (!net || !lines || !out || n < 1 || pixels < 2 || !(momentum > 0.f && momentum <= 1.f))
+        return fail(ERX_EINVAL, "erx_surrogate_scores: invalid arguments");
+    if (!is_device(lines) || !is_device(out)) return fail(ERX_EINVAL, "lines and out must be device memory");
+    if (((uintptr_t)lines % 4) || ((uintptr_t)out % 4)) return fail(ERX_EINVAL, "buffers must be 4-byte aligned");
+    HIPCHK(net->erx.ensure(n, pixels));
+    if (!net->dummy) HIPCHK(hipMalloc(&net->dummy, (size_t)net->erx.cap * net->erx.capp * sizeof(float)));
+    HIPCHK(hipMemsetAsync(net->erx.state, 0, stat_entries(1) * sizeof(double), net->stream));
+    HIPCHK(net_forward(net, net->stream, net->erx, lines, n, pixels, momentum, 0, out, net->dummy));
+    HIPCHK(hipStreamSynchronize(net->stream));
+    return ERX_OK;
+}
+
+int erx_surrogate_train_step(erx_surr* net, const float* lines, const float* targets, int n, int pixels,
+                             float momentum, float lr, float* loss)
+{
+    if (!net || !lines || !targets || n < 1 || pixels < 2 || !(momentum > 0.f && momentum <= 1.f) || !(lr >= 0.f))
+        return fail(ERX_EINVAL, "erx_surrogate_train_step: invalid arguments");
+    if (!is_device(lines) || !is_device(targets)) return fail(ERX_EINVAL, "lines and targets must be device memory");
+    if (((uintptr_t)lines % 4) || ((uintptr_t)targets % 4)) return fail(ERX_EINVAL, "buffers must be 4-byte aligned");
+    hipStream_t s = net->stream;
+    HIPCHK(net->erx.ensure(n, pixels));
+    const long long N = (long long)n * pixels;
+    if (N > net->capN || !net->dummy) {
+        void* d[] = {net->U, net->Pre, net->G, net->dZ, net->dummy};
+        for (void* q : d)
+            if (q) (void)hipFree(q);
+        const long long C = std::max<long long>(N, (long long)net->erx.cap * net->erx.capp);
+        if (hipMalloc(&net->U, C * SK * sizeof(float)) != hipSuccess ||
+            hipMalloc(&net->Pre, C * SH * sizeof(float)) != hipSuccess ||
+            hipMalloc(&net->G, C * sizeof(float)) != hipSuccess ||
+            hipMalloc(&net->dZ, C * SK * sizeof(float)) != hipSuccess ||
+            hipMalloc(&net->dummy, C * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            net->U = net->Pre = net->G = net->dZ = net->dummy = nullptr;
+            net->capN = 0;
+            return fail(ERX_ENOMEM, "erx_surrogate_train_step: cannot allocate the workspace");
+        }
+        net->capN = C;
+    }
+    // forward pass of the projection and the ERX statistics of the z stream
+    HIPCHK(hipMemsetAsync(net->erx.state, 0, stat_entries(1) * sizeof(double), s));
+    HIPCHK(project(net, s, net->erx, lines, N, 0));
+    HIPCHK(net->erx.pass(s, n, pixels, momentum, 0, net->dummy));
+    // per-pixel forward and backward, then the gradient sums
+    HIPCHK(hipMemsetAsync(net->loss, 0, sizeof(float), s));
+    HIPCHK(hipMemsetAsync(net->grad, 0, net->off.n * sizeof(float), s));
+    const int ngrp = (pixels + 255) / 256;
+    hipLaunchKernelGGL((k_surr_pix<true>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, net->erx.Z,
+                       pixels, ngrp, net->erx.Mt, net->erx.mu32, net->P, net->off.A1, net->off.a1, net->off.w2,
+                       net->off.c2, nullptr, targets, net->U, net->Pre, net->G, net->dZ, net->loss,
+                       (float)(1.0 / (double)N));
+    HIPCHK(hipGetLastError());
+    const int chunk = 256;
+    const long long nch = (N + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_surr_reduce, dim3((unsigned)((net->off.n + 255) / 256), (unsigned)nch), dim3(256), 0, s,
+                       lines, net->b, N, chunk, net->U, net->Pre, net->G, net->dZ, net->P, net->grad);
+    HIPCHK(hipGetLastError());
+    if (lr > 0.f) {
+        ++net->step;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - std::pow(b1, (float)net->step), c2 = 1.f - std::pow(b2, (float)net->step);
+        hipLaunchKernelGGL(k_adam, dim3((net->off.n + 255) / 256), dim3(256), 0, s, net->P, net->grad, net->m, net->v,
+                           net->W16, net->off.n, SK * net->b, lr, b1, b2, 1e-8f, c1, c2);
+        HIPCHK(hipGetLastError());
+    }
+    float l = 0.f;
+    HIPCHK(hipMemcpyAsync(&l, net->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (loss) *loss = l;
+    return ERX_OK;
+}
+
+int erx_surrogate_grads(const erx_surr* net, float* grads)
+{
+    if (!net || !grads) return fail(ERX_EINVAL, "NULL argument");
+    HIPCHK(hipMemcpyAsync(grads, net->grad, net->off.n * sizeof(float), hipMemcpyDeviceToHost, net->stream));
+    HIPCHK(hipStreamSynchronize(net->stream));
+    return ERX_OK;
+}
+
+// ------------------------------------------------------------ surrogate detector
+erx_sdet* erx_surrogate_detector_create(erx_surr* net, int pixels, float momentum, float drift_threshold,
+                                        int check_every)
+{
+    if (!net || pixels < 2 || !(momentum > 0.f && momentum <= 1.f) || !(drift_threshold > 0.f) || check_every < 1) {
+        fail(ERX_EINVAL, "erx_surrogate_detector_create: invalid arguments");
+        return nullptr;
+    }
+    erx_sdet* sd = new (std::nothrow) erx_sdet();
+    if (!sd) {
+        fail(ERX_ENOMEM, "out of host memory");
+        return nullptr;
+    }
+    sd->net = net;
+    sd->p = pixels;
+    sd->alpha = momentum;
+    sd->theta = drift_threshold;
+    sd->R = check_every;
+    sd->alpha_r = (float)(1.0 - std::pow(1.0 - (double)momentum, (double)check_every));
+    erx_config c;
+    erx_config_default(&c, net->b, pixels, sd->alpha_r);
+    c.block_lines = 1;
+    c.scan_lines = 1;
+    sd->monitor = erx_create_ex(&c);
+    bool ok = sd->monitor && hipStreamCreateWithFlags(&sd->stream, hipStreamNonBlocking) == hipSuccess &&
+              erx_set_stream(sd->monitor, sd->stream) == ERX_OK &&
+              hipMalloc(&sd->dummy, (size_t)pixels * 256 * sizeof(float)) == hipSuccess &&
+              hipMalloc(&sd->mscore, (size_t)pixels * sizeof(float)) == hipSuccess &&
+              sd->erx.ensure(256, pixels) == hipSuccess && sd->mon16.ensure(1, pixels) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        erx_surrogate_detector_destroy(sd);
+        fail(ERX_ENOMEM, "erx_surrogate_detector_create: allocation failed");
+        return nullptr;
+    }
+    return sd;
+}
+
+void erx_surrogate_detector_destroy(erx_sdet* sd)
+{
+    if (!sd) return;
+    if (sd->stream) (void)hipStreamSynchronize(sd->stream);
+    if (sd->monitor) erx_destroy(sd->monitor);
+    if (sd->plain) erx_destroy(sd->plain);
+    if (sd->scores) (void)hipFree(sd->scores);
+    if (sd->dummy) (void)hipFree(sd->dummy);
+    if (sd->mscore) (void)hipFree(sd->mscore);
+    sd->erx.release();
+    sd->mon16.release();
+    if (sd->stream) (void)hipStreamDestroy(sd->stream);
+    delete sd;
+}
+
+int erx_surrogate_detector_push(erx_sdet* sd, const float* lines, int n)
+{
+    if (!sd || !lines || n < 1) return fail(ERX_EINVAL, "erx_surrogate_detector_push: invalid arguments");
+    if (!is_device(lines) || ((uintptr_t)lines % 4)) return fail(ERX_EINVAL, "lines must be aligned device memory");
+    const int p = sd->p, b = sd->net->b;
+    if (n > sd->cap) {
+        if (sd->scores) (void)hipFree(sd->scores);
+        sd->scores = nullptr;
+        if (hipMalloc(&sd->scores, (size_t)n * p * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            sd->cap = 0;
+            return fail(ERX_ENOMEM, "cannot allocate the score buffer");
+        }
+        sd->cap = n;
+    }
+    hipStream_t s = sd->stream;
+    const size_t lsz = (size_t)p * b;
+    int done = 0;
+    while (done < n) {
+        if (!sd->active) {  // plain ERX from here on
+            const int k = n - done;
+            if (erx_push_lines_ex(sd->plain, lines + (size_t)done * lsz, k) != ERX_OK) return ERX_EDEVICE;
+            const int rc = erx_scores_device(sd->plain, sd->scores + (size_t)done * p);
+            if (rc != ERX_OK && rc != ERX_ENOTPD) return rc;
+            done = n;
+            break;
+        }
+        // surrogate block up to (and including) the next check line
+        const long long t0 = sd->t + done;
+        const long long next_check = ((t0 / sd->R) + 1) * sd->R - 1;  // global index of the next check line
+        const int k = (int)std::min<long long>({(long long)(n - done), next_check - t0 + 1, 256});
+        const float* X = lines + (size_t)done * lsz;
+        HIPCHK(net_forward(sd->net, s, sd->erx, X, k, p, sd->alpha, t0, sd->scores + (size_t)done * p, sd->dummy));
+        done += k;
+        const long long last = t0 + k - 1;
+        if (last == next_check) {  // the check line: plain ERX on the monitor state
+            const float* xc = lines + (size_t)(done - 1) * lsz;
+            if (erx_push_lines_ex(sd->monitor, xc, 1) != ERX_OK) return ERX_EDEVICE;
+            HIPCHK(net_forward(sd->net, s, sd->mon16, xc, 1, p, sd->alpha_r, sd->checks, sd->mscore, sd->dummy));
+            sd->hs.resize(p);
+            sd->hp.resize(p);
+            HIPCHK(hipMemcpyAsync(sd->hs.data(), sd->mscore, p * sizeof(float), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const int rc = erx_scores(sd->monitor, sd->hp.data());
+            if (rc != ERX_OK && rc != ERX_ENOTPD) return rc;
+            std::vector<float> dev(p);
+            for (int i = 0; i < p; ++i) dev[i] = std::fabs(std::log(sd->hs[i]) - std::log(sd->hp[i]));
+            std::nth_element(dev.begin(), dev.begin() + p / 2, dev.end());
+            float med = dev[p / 2];
+            if (!(p & 1)) {
+                const float lo = *std::max_element(dev.begin(), dev.begin() + p / 2);
+                med = 0.5f * (med + lo);
+            }
+            ++sd->checks;
+            const bool drift = !(med <= sd->theta);  // NaN counts as drift
+            sd->drifts += drift ? 1 : 0;
+            sd->drift_run = drift ? sd->drift_run + 1 : 0;
+            if (sd->drift_run >= 2) {
+                erx_config c;
+                erx_config_default(&c, b, p, sd->alpha);
+                sd->plain = erx_create_ex(&c);
+                if (!sd->plain) return ERX_ENOMEM;
+                if (erx_set_stream(sd->plain, s) != ERX_OK) return ERX_EDEVICE;
+                sd->active = false;
+                sd->switched_at = last + 1;
+            }
+        }
+    }
+    sd->t += n;
+    sd->last_n = n;
+    return ERX_OK;
+}
+
+int erx_surrogate_detector_scores(erx_sdet* sd, float* out)
+{
+    if (!sd || !out) return fail(ERX_EINVAL, "NULL argument");
+    if (sd->last_n == 0) return fail(ERX_ESTATE, "no lines pushed yet");
+    HIPCHK(hipMemcpyAsync(out, sd->scores, (size_t)sd->last_n * sd->p * sizeof(float), hipMemcpyDefault,
+                          sd->stream));
+    HIPCHK(hipStreamSynchronize(sd->stream));
+    return ERX_OK;
+}
+
+int erx_surrogate_detector_status(const erx_sdet* sd, int* active, long long* checks, long long* drifts,
+                                  long long* switched_at)
+{
+    if (!sd) return fail(ERX_EINVAL, "NULL detector");
+    if (active) *active = sd->active ? 1 : 0;
+    if (checks) *checks = sd->checks;
+    if (drifts) *drifts = sd->drifts;
+    if (switched_at) *switched_at = sd->switched_at;
+    return ERX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+"""The learned projection surrogate on the GPU against its FP64 reference
+(oracle/surrogate.py): forward scores and loss gradients for the same
+parameters, training behaviour, and the checked detector with its switch to
+plain ERX."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(f"[gpu-surrogate] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def erx():
+    import paper_2408_14947_amd as m
+    m.load()
+    return m
+
+
+def rel_err(got, want):
+    got = np.asarray(got, np.float64)
+    return np.abs(got - want) / np.maximum(np.abs(want), 1.0)
+
+
+def gpu_exact_params(bands, seed, w2_scale=0.3):
+    """Parameters representable exactly by the GPU copy (FP16 W, FP32 rest)."""
+    P = S.init_params(bands, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    P["w2"] = rng.normal(0, w2_scale, S.HIDDEN)
+    P["a1"] = rng.normal(0, 0.3, S.HIDDEN)
+    P["c"] = rng.normal(0, 0.1, S.K)
+    P["c2"] = np.array([0.1])
+    P["W"] = P["W"].astype(np.float16).astype(np.float64)
+    for k in ("c", "A1", "a1", "w2", "c2"):
+        P[k] = P[k].astype(np.float32).astype(np.float64)
+    return P
+
+
+@pytest.mark.parametrize("b,p,T", [(37, 300, 20), (108, 256, 12), (16, 1000, 6)])
+def test_forward_matches_reference(erx, b, p, T):
+    log(f"forward b={b} p={p} T={T}")
+    sc = datagen.make_scene(61, b, b, p, T)
+    X = datagen.lines(sc, 0, T)[0]
+    P = gpu_exact_params(b, 3)
+    net = erx.Surrogate(b)
+    net.set_params(P)
+    got = net.scores(X.cuda(), 0.1).cpu().numpy()
+    want = S.forward(P, X.numpy(), 0.1)["score"]
+    err = rel_err(got, want)
+    log(f"  max err {err.max():.2e}")
+    assert err.max() <= 2e-4
+
+
+def test_gradients_match_reference(erx):
+    b, p, T = 40, 200, 10
+    log("gradients")
+    sc = datagen.make_scene(62, 0, b, p, T)
+    X = datagen.lines(sc, 0, T)[0]
+    P = gpu_exact_params(b, 5)
+    target = oracle.run(X.numpy(), 0.1)["delta"]
+    net = erx.Surrogate(b)
+    net.set_params(P)
+    loss = net.train_step(X.cuda(), torch.from_numpy(target.astype(np.float32)).cuda(), 0.1, 0.0)
+    g = net.grads()
+    want_loss, want, _ = S.loss_and_grads(P, X.numpy(), target, 0.1)
+    assert abs(loss - want_loss) <= 1e-3 * max(want_loss, 1e-3), (loss, want_loss)
+    for name in S.PARAM_NAMES:
+        a = np.asarray(g[name], np.float64).reshape(-1)
+        w = np.asarray(want[name], np.float64).reshape(-1)
+        err = np.linalg.norm(a - w) / max(np.linalg.norm(w), 1e-12)
+        log(f"  {name}: relative error {err:.2e}")
+        assert err <= 2e-3, name
+    # no step with lr = 0
+    P2 = net.params()
+    for name in S.PARAM_NAMES:
+        np.testing.assert_array_equal(np.asarray(P2[name], np.float64).reshape(-1),
+                                      np.asarray(P[name], np.float32).astype(np.float64).reshape(-1))
+
+
+def test_training_lowers_the_loss(erx):
+    b, p, T = 48, 256, 16
+    log("training")
+    net = erx.Surrogate(b, seed=1)
+    det_losses = []
+    for step in range(60):
+        sc = datagen.make_scene(63, step, b, p, T)
+        X = datagen.lines(sc, 0, T)[0].cuda()
+        d = erx.Detector(b, p, 0.1)
+        d.push(X)
+        tgt = d.scores()
+        det_losses.append(net.train_step(X, tgt, 0.1, 3e-3))
+        d.close()
+    first, last = np.mean(det_losses[:5]), np.mean(det_losses[-5:])
+    log(f"  loss {first:.3f} -> {last:.3f}")
+    assert last < 0.5 * first
+
+
+def test_detector_identity_network_stays_and_matches_erx(erx):
+    """W orthogonal (b = 16), network output 0: the surrogate is plain ERX, so
+    every check sees no drift and the scores equal plain ERX."""
+    b, p, T, R = 16, 128, 70, 8
+    sc = datagen.make_scene(64, 0, b, p, T)
+    X = datagen.lines(sc, 0, T)[0]
+    Q, _ = np.linalg.qr(np.random.default_rng(3).normal(size=(b, b)))
+    P = gpu_exact_params(b, 7)
+    P["W"] = np.eye(b)
+    P["c"] = np.zeros(b)
+    P["w2"] = np.zeros(S.HIDDEN)
+    P["c2"] = np.zeros(1)
+    net = erx.Surrogate(b)
+    net.set_params(P)
+    det = erx.SurrogateDetector(net, p, 0.1, drift_threshold=0.05, check_every=R)
+    Xd = X.cuda()
+    det.push(Xd[:30])
+    a = det.scores().cpu().numpy()
+    det.push(Xd[30:])
+    bb = det.scores().cpu().numpy()
+    got = np.concatenate([a, bb])
+    want = oracle.run(X.numpy(), 0.1)["delta"]
+    err = rel_err(got, want)
+    li, pi = np.unravel_index(np.argmax(err), err.shape)
+    log(f"  max err {err.max():.2e} at line {li} pixel {pi}; per-line max {np.round(err.max(1), 6).tolist()}")
+    assert err.max() <= 2e-4
+    st = det.status()
+    log(f"  status {st}")
+    assert st["active"] and st["checks"] == T // R and st["drifts"] == 0
+
+
+def test_detector_switches_to_plain_erx_on_drift(erx):
+    """A network biased by exp(0.4): every check drifts by 0.4 > 0.05, so after
+    the second check (line 2R-1) the stream is plain ERX from line 2R on,
+    initialised from that line."""
+    b, p, T, R = 24, 96, 60, 10
+    sc = datagen.make_scene(65, 0, b, p, T)
+    X = datagen.lines(sc, 0, T)[0]
+    P = gpu_exact_params(b, 9)
+    P["w2"] = np.zeros(S.HIDDEN)
+    P["c2"] = np.array([0.4], np.float32).astype(np.float64)
+    net = erx.Surrogate(b)
+    net.set_params(P)
+    det = erx.SurrogateDetector(net, p, 0.1, drift_threshold=0.05, check_every=R)
+    det.push(X.cuda())
+    got = det.scores().cpu().numpy()
+    st = det.status()
+    log(f"  status {st}")
+    assert not st["active"] and st["switched_at"] == 2 * R and st["checks"] == 2 and st["drifts"] == 2
+    surr = S.forward(P, X.numpy()[:2 * R], 0.1)["score"]
+    assert rel_err(got[:2 * R], surr).max() <= 2e-4
+    plain = oracle.run(X.numpy()[2 * R:], 0.1)["delta"]
+    assert rel_err(got[2 * R:], plain).max() <= 1e-4
