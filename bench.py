@@ -240,6 +240,129 @@ def batched_leg(erx, torch, cfg, T, stream, mixed):
     return res
 
 
+def srp_matrix(bands, d, seed):
+    """Sparse random projection of Sec. III-B as a d x b matrix (the transpose of the paper's
+    b x d W): entries sqrt(s/d) * {+1, 0, -1} with probabilities 1/(2s), 1 - 1/s, 1/(2s),
+    s = sqrt(b)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    s = np.sqrt(bands)
+    u = rng.random((d, bands))
+    w = np.where(u < 1 / (2 * s), 1.0, np.where(u < 1 / s, -1.0, 0.0))
+    return np.sqrt(s / d) * w
+
+
+def surrogate_leg(erx, torch, stream, steps):
+    """Learned projection surrogate: training on fresh synthetic lines (targets: the plain GPU
+    path), then on held-out streams the error against plain ERX, per-line rank agreement,
+    anomaly AUC and throughput, next to ERX on a sparse random projection (Sec. III-B) and on
+    a dense Gaussian projection to the same 16 dimensions (no network)."""
+    import numpy as np
+    import datagen
+    res = {}
+    a = datagen.CONFIGS[5]["momentum"]
+
+    def ranks(x):
+        return torch.argsort(torch.argsort(x, dim=-1), dim=-1).double()
+
+    def auc(score, mask):
+        s = score.flatten().double()
+        m = mask.flatten()
+        r = ranks(s[None])[0] + 1
+        npos, nneg = int(m.sum()), int((~m).sum())
+        return float((r[m].sum() - npos * (npos + 1) / 2) / (npos * nneg))
+
+    def compare(got, ref):
+        lr = (torch.log(got.double()) - torch.log(ref.double())).abs().flatten()
+        k = max(1, lr.numel() // 100)
+        rg, rr = ranks(got.double()), ranks(ref.double())
+        rg -= rg.mean(-1, keepdim=True)
+        rr -= rr.mean(-1, keepdim=True)
+        sp = (rg * rr).sum(-1) / torch.sqrt((rg * rg).sum(-1) * (rr * rr).sum(-1))
+        return {"median_abs_log_ratio": float(lr.median()), "p99_abs_log_ratio": float(torch.topk(lr, k).values.min()),
+                "mean_line_spearman": float(sp.mean())}
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    for b in (108, 224):
+        net = erx.Surrogate(b, seed=b)
+        p_tr, T_tr = 640, 32
+        losses = []
+        with torch.cuda.stream(stream):
+            for k in range(steps):
+                sc = datagen.make_scene(5, 1000 + k, b, p_tr, T_tr, momentum=a)
+                X = datagen.lines(sc, 0, T_tr, device="cuda")[0]
+                d = erx.Detector(b, p_tr, a, block_lines=T_tr, stream=stream.cuda_stream)
+                d.push(X)
+                tgt = d.scores()
+                lr = 3e-3 if k < steps * 3 // 4 else 1e-3
+                losses.append(net.train_step(X, tgt, a, lr))
+                d.close()
+        # held-out streams
+        Hs, T_h, p_h = 2, 256, 1024
+        rows = {"plain": [], "surrogate": [], "surrogate_unchecked": [], "srp16": [], "gauss16": []}
+        masks, ms = [], {"plain": 0.0, "surrogate": 0.0, "surrogate_unchecked": 0.0}
+        status = []
+        srp = erx.Surrogate(b)
+        gau = erx.Surrogate(b)
+        base = net.params()
+        for name, W in (("srp", srp_matrix(b, 16, 7)), ("gau", np.random.default_rng(8).normal(0, 1 / np.sqrt(16), (16, b)))):
+            P = {k: np.zeros_like(v) for k, v in base.items()}
+            P["W"] = W
+            P["A1"] = base["A1"]
+            (srp if name == "srp" else gau).set_params(P)
+        for i in range(Hs):
+            sc = datagen.make_scene(5, 90000 + i, b, p_h, T_h, momentum=a)
+            with torch.cuda.stream(stream):
+                X, M = datagen.lines(sc, 0, T_h, device="cuda")
+            torch.cuda.synchronize()
+            det = erx.Detector(b, p_h, a, block_lines=T_h, stream=stream.cuda_stream)
+            det.push(X)  # warm-up of the handle's kernels
+            det.close()
+            det = erx.Detector(b, p_h, a, block_lines=T_h, stream=stream.cuda_stream)
+            _, t = timed(lambda: det.push(X))
+            ms["plain"] += t
+            rows["plain"].append(det.scores())
+            sd = erx.SurrogateDetector(net, p_h, a, drift_threshold=0.05, check_every=32)
+            _, t = timed(lambda: sd.push(X))
+            ms["surrogate"] += t
+            rows["surrogate"].append(sd.scores())
+            status.append(sd.status())
+            net.scores(X[:8], a)  # warm-up
+            su, t = timed(lambda: net.scores(X, a))
+            ms["surrogate_unchecked"] += t
+            rows["surrogate_unchecked"].append(su)
+            rows["srp16"].append(srp.scores(X, a))
+            rows["gauss16"].append(gau.scores(X, a))
+            masks.append(M)
+            det.close()
+            sd.close()
+        mask = torch.cat(masks)
+        cat = {k: torch.cat(v) for k, v in rows.items()}
+        npx = Hs * T_h * p_h
+        r = {"train": {"steps": steps, "lines_per_step": T_tr, "pixels": p_tr,
+                       "loss_first10": float(np.mean(losses[:10])), "loss_last10": float(np.mean(losses[-10:]))},
+             "held_out": f"{Hs} streams x {T_h} lines x {p_h} px, seeds disjoint from training",
+             "auc": {k: auc(v, mask) for k, v in cat.items()},
+             "vs_plain": {k: compare(cat[k], cat["plain"])
+                          for k in ("surrogate", "surrogate_unchecked", "srp16", "gauss16")},
+             "pixels_per_s": {"plain": npx / (ms["plain"] / 1e3), "surrogate_checked": npx / (ms["surrogate"] / 1e3),
+                              "surrogate_unchecked": npx / (ms["surrogate_unchecked"] / 1e3)},
+             "detector_status": status}
+        res[f"b{b}"] = r
+        net.close()
+        srp.close()
+        gau.close()
+    return res
+
+
 # frozen error bounds of the reduced-precision Gram (max, p99 of the relative score error)
 MIXED_BOUNDS = {"bf16": (1e-2, 3e-3), "fp16": (1e-3, 5e-4)}
 
@@ -305,6 +428,9 @@ def main():
                     help="skip the many-stream side measurements (batched-u16, batched-multispectral-f16)")
     ap.add_argument("--batched-lines", type=int, default=128,
                     help="lines per stream in the many-stream side measurements")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the learned-projection surrogate side measurement")
+    ap.add_argument("--surrogate-steps", type=int, default=200, help="training steps per band count")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known traffic against "
                          "which the FETCH_SIZE / WRITE_SIZE counters are scaled)")
@@ -419,6 +545,10 @@ def main():
         print("[bench] many-stream workloads", file=sys.stderr, flush=True)
         out["batched_u16"] = batched_leg(erx, torch, 3, args.batched_lines, stream, mixed=True)
         out["batched_multispectral_f16"] = batched_leg(erx, torch, 4, args.batched_lines, stream, mixed=False)
+
+    if not args.no_surrogate:
+        print("[bench] learned projection surrogate", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_leg(erx, torch, stream, args.surrogate_steps)
 
     if not args.no_cpu_baseline:
         import oracle

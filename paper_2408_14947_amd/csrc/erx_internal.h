@@ -1,6 +1,7 @@
 // Internal declarations shared by the kernels and the C-ABI runtime.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
 #include "../../include/erx.h"
 
@@ -56,6 +57,9 @@ hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double*
                        unsigned long long* ctr, hipStream_t s);
 hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s);
 hipError_t launch_normalise(const Pass& P, hipStream_t s);
+// surrogate projection z - zref = W (x - xref) for npx FP32 pixels of b bands (W: FP16 [16][b])
+hipError_t launch_sproj(const float* X, long long npx, int b, const __half* W16, const float* xref, float* Z,
+                        hipStream_t s);
 // exact (FP64) statistics of one-tile FP32 streams, in the k_gram layout
 hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s);
 // fused path for streams with at most 16 bands: one workgroup per stream, its

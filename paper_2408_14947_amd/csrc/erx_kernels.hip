@@ -1774,6 +1774,66 @@ __global__ __launch_bounds__(256) void k_gram1x(const Pass P, double* __restrict
     if (g == 0) ls[256 + c] = (c < b) ? m_c : 0.0;
 }
 
+// ============================================================================
+// Projection of the learned surrogate: z - zref = W (x - xref) on FP32 matrix
+// cores, with xref the stream's first pixel and zref = W xref + c.  ERX is
+// exactly invariant to a constant shift of its input, and subtracting xref
+// before the product keeps the accumulated values (and their FP32 rounding) at
+// the scale of the data's spread, which is what the statistics of the z stream
+// resolve.  A wave projects 16-pixel tiles: lane (g, c) supplies bands
+// 16K+4g..16K+4g+3 of pixel c and holds the W tile of those bands in operand
+// form, so four 16x16x4 MFMAs per 16 bands accumulate the 16 outputs of the 16
+// pixels (outputs 4g..4g+3 of pixel c in lane (g, c)).  W is FP16.
+// ============================================================================
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_sproj(const float* __restrict__ X, long long npx, int b, int NTx,
+                                               const __half* __restrict__ W16, const float* __restrict__ xref,
+                                               float* __restrict__ Z)
+{
+    extern __shared__ f4 Wt[];  // [NTx][64] W tiles in operand form, then xref [16 NTx]
+    float* xr_s = (float*)(Wt + NTx * 64);
+    for (int i = threadIdx.x; i < NTx * 64; i += 256) {
+        const int K = i >> 6, l = i & 63, g = l >> 4, c = l & 15;
+        f4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int band = 16 * K + 4 * g + q;
+            v[q] = band < b ? __half2float(W16[c * b + band]) : 0.f;
+        }
+        Wt[i] = v;
+    }
+    for (int i = threadIdx.x; i < 16 * NTx; i += 256) xr_s[i] = i < b ? xref[i] : 0.f;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const long long px = ((long long)blockIdx.x * 4 + w) * 16 + c;
+    const bool okp = px < npx;
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int K = 0; K < NTx; ++K) {
+        const int band0 = 16 * K + 4 * g;
+        const bool okl = okp && band0 < b;
+        const f4 v = ldq<DT_F32, VEC>(X, okl ? (size_t)px * b + band0 : 0, okl ? b - band0 : 0);
+        f4 r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] = (okl && band0 + q < b) ? v[q] - xr_s[band0 + q] : 0.f;
+        acc = mma_xty(acc, Wt[K * 64 + lane], r);
+    }
+    if (okp) *(f4*)(Z + px * 16 + 4 * g) = acc;
+}
+
+hipError_t launch_sproj(const float* X, long long npx, int b, const __half* W16, const float* xref, float* Z,
+                        hipStream_t s)
+{
+    const int NTx = (b + 15) / 16;
+    const size_t lds = (size_t)NTx * 64 * sizeof(f4) + 16 * NTx * sizeof(float);
+    const dim3 grid((unsigned)((npx + 63) / 64));
+    if (b % 4 == 0 && (uintptr_t)X % 16 == 0)
+        hipLaunchKernelGGL(k_sproj<true>, grid, dim3(256), lds, s, X, npx, b, NTx, W16, xref, Z);
+    else
+        hipLaunchKernelGGL(k_sproj<false>, grid, dim3(256), lds, s, X, npx, b, NTx, W16, xref, Z);
+    return hipGetLastError();
+}
+
 hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gram1x, dim3((unsigned)P.nlines), dim3(256), 0, s, P, stats, stat_entries(1));

@@ -66,57 +66,6 @@ __host__ __device__ inline Off offsets(int b)
 }
 
 // ---------------------------------------------------------------- kernels
-// z = W x + c - zref, one thread per pixel, accumulated in FP64; W (FP16)
-// transposed in LDS so that every lane reads the same words (broadcast).
-// zref is a per-stream constant (the projection of the stream's first pixel):
-// ERX is exactly invariant to a constant shift of its input, and storing the
-// shifted projection in FP32 keeps its rounding small relative to the spread
-// of the data, which is what the statistics of the z stream resolve.
-__global__ __launch_bounds__(256) void k_sproj(const float* __restrict__ X, long long npx, int b,
-                                               const __half* __restrict__ W16, const float* __restrict__ P,
-                                               int offc, const double* __restrict__ zref, float* __restrict__ Z)
-{
-    extern __shared__ float Ws[];  // [b][16]
-    for (int i = threadIdx.x; i < SK * b; i += 256) {
-        const int o = i / b, k = i - o * b;
-        Ws[k * SK + o] = __half2float(W16[i]);
-    }
-    __syncthreads();
-    const long long px = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (px >= npx) return;  // no barrier follows
-    double z[SK];
-#pragma unroll
-    for (int o = 0; o < SK; ++o) z[o] = (double)P[offc + o] - zref[o];
-    const float* xr = X + px * b;
-    for (int k = 0; k < b; ++k) {
-        const double xk = (double)xr[k];
-        const float4* wk = (const float4*)&Ws[k * SK];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 w = wk[q];
-            z[4 * q + 0] += (double)w.x * xk;
-            z[4 * q + 1] += (double)w.y * xk;
-            z[4 * q + 2] += (double)w.z * xk;
-            z[4 * q + 3] += (double)w.w * xk;
-        }
-    }
-    float4* zo = (float4*)(Z + px * SK);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        zo[q] = make_float4((float)z[4 * q], (float)z[4 * q + 1], (float)z[4 * q + 2], (float)z[4 * q + 3]);
-}
-
-// zref = W x0 + c for one pixel x0 (FP64), one thread per output
-__global__ __launch_bounds__(64) void k_zref(const float* __restrict__ x0, int b, const __half* __restrict__ W16,
-                                             const float* __restrict__ P, int offc, double* __restrict__ zref)
-{
-    const int o = threadIdx.x;
-    if (o >= SK) return;
-    double s = (double)P[offc + o];
-    for (int k = 0; k < b; ++k) s += (double)__half2float(W16[o * b + k]) * (double)x0[k];
-    zref[o] = s;
-}
-
 // Per pixel: u = M (z - mu), the network, the score; with TRAIN also the loss
 // term, d loss / d log score (G), the hidden pre-activations, u and
 // d loss / dz, for the reduction kernel.  One workgroup per (line, 256
@@ -288,11 +237,11 @@ struct Erx16 {
     int* flags = nullptr;
     float* cond = nullptr;
     double* state = nullptr;
-    double* zref = nullptr;
+    float* xref = nullptr;  // the stream's first pixel
     unsigned long long* ctr = nullptr;
     void release()
     {
-        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond, state, zref, ctr};
+        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond, state, xref, ctr};
         for (void* q : d)
             if (q) (void)hipFree(q);
         *this = Erx16();
@@ -301,7 +250,7 @@ struct Erx16 {
     {
         if (!state) {
             if (hipMalloc(&state, stat_entries(1) * sizeof(double)) != hipSuccess ||
-                hipMalloc(&zref, SK * sizeof(double)) != hipSuccess ||
+                hipMalloc(&xref, ERX_MAX_BANDS * sizeof(float)) != hipSuccess ||
                 hipMalloc(&ctr, 4 * sizeof(unsigned long long)) != hipSuccess ||
                 hipMemset(state, 0, stat_entries(1) * sizeof(double)) != hipSuccess ||
                 hipMemset(ctr, 0, 4 * sizeof(unsigned long long)) != hipSuccess)
@@ -419,13 +368,14 @@ struct erx_sdet {
 namespace {
 
 // projection of n lines into erx.Z; at the first line of a stream (t0 == 0)
-// the stream's reference zref is set from its first pixel
+// the stream's reference pixel xref is set to its first pixel
 hipError_t project(erx_surr* net, hipStream_t s, Erx16& erx, const float* X, long long npx, long long t0)
 {
-    if (t0 == 0) hipLaunchKernelGGL(k_zref, dim3(1), dim3(64), 0, s, X, net->b, net->W16, net->P, net->off.c, erx.zref);
-    hipLaunchKernelGGL(k_sproj, dim3((unsigned)((npx + 255) / 256)), dim3(256), SK * net->b * sizeof(float), s, X,
-                       npx, net->b, net->W16, net->P, net->off.c, erx.zref, erx.Z);
-    return hipGetLastError();
+    if (t0 == 0) {
+        const hipError_t e = hipMemcpyAsync(erx.xref, X, net->b * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_sproj(X, npx, net->b, net->W16, erx.xref, erx.Z, s);
 }
 
 hipError_t net_forward(erx_surr* net, hipStream_t s, Erx16& erx, const float* X, int n, int p, double alpha,
