@@ -41,7 +41,7 @@ def short_kernel(name):
     k = m.group(1)
     if k == "chol":
         return "chol_fp64" if (m.group(3) or "").startswith("double") else "chol_fp32"
-    return k
+    return {"gram4": "gram"}.get(k, k)
 
 
 def _csv_rows(d, suffix):
