@@ -397,7 +397,9 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         sr[j] = sc[j] = 0.f;
         dsr[j] = dsc[j] = 0.0;
     }
-    auto stage = [&](int k0) __attribute__((always_inline)) {
+    auto stage = [&](int k0, int buf) __attribute__((always_inline)) {
+        uint32_t* Rb = Rt + buf * G::WORDS;
+        uint32_t* Cb = Ct + buf * G::WORDS;
         const int nv = p - k0 - 4 * pq;  // valid pixels among this thread's four
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -405,16 +407,15 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = (r < nv && rok[j]) ? pr[r][j] - shr[j] : 0.f;
             sr[j] += (v[0] + v[1]) + (v[2] + v[3]);
-            G::put(Rt, 4 * bg + j, pq, v);
+            G::put(Rb, 4 * bg + j, pq, v);
             if (!dg) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = (r < nv && cok[j]) ? pc[r][j] - shc[j] : 0.f;
                 sc[j] += (v[0] + v[1]) + (v[2] + v[3]);
-                G::put(Ct, 4 * bg + j, pq, v);
+                G::put(Cb, 4 * bg + j, pq, v);
             }
         }
     };
-    const uint32_t* Cp = dg ? (const uint32_t*)Rt : (const uint32_t*)Ct;
 
     const int nq = __builtin_amdgcn_readfirstlane((NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4);
     int tbits = 0;
@@ -431,17 +432,24 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < p; k0 += 64) {
-        stage(k0);
-        __syncthreads();
-        fetch(k0 + 64);  // next chunk in flight during the products
+    // Double-buffered LDS: the products of chunk j read buffer j & 1 while the
+    // staging of chunk j+1 (from registers) fills the other buffer and the
+    // loads of chunk j+2 are issued; one barrier per chunk.  Staging and
+    // fetching run unconditionally (past the last pixel they stage zeros and
+    // load clamped addresses), so no load sits under a branch.
+    stage(0, 0);
+    fetch(64);
+    __syncthreads();
+    for (int k0 = 0, it = 0; k0 < p; k0 += 64, ++it) {
+        const uint32_t* Rb = Rt + (it & 1) * G::WORDS;
+        const uint32_t* Cb = dg ? Rb : (const uint32_t*)(Ct + (it & 1) * G::WORDS);
         if (rowok) {
             const int kend = (p - k0) < 64 ? (p - k0) : 64;
             switch (nq) {
-            case 1: G::template chunk<1>(Rt, Cp, w, c, g, kend, acc); break;
-            case 2: G::template chunk<2>(Rt, Cp, w, c, g, kend, acc); break;
-            case 3: G::template chunk<3>(Rt, Cp, w, c, g, kend, acc); break;
-            default: G::template chunk<4>(Rt, Cp, w, c, g, kend, acc); break;
+            case 1: G::template chunk<1>(Rb, Cb, w, c, g, kend, acc); break;
+            case 2: G::template chunk<2>(Rb, Cb, w, c, g, kend, acc); break;
+            case 3: G::template chunk<3>(Rb, Cb, w, c, g, kend, acc); break;
+            default: G::template chunk<4>(Rb, Cb, w, c, g, kend, acc); break;
             }
         }
         if (((k0 + 64) % G::FLUSH) == 0 || k0 + 64 >= p) {
@@ -452,13 +460,20 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
                 acc[q] = f4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 4; ++j) {  // band sums of the chunks staged so far
                 dsr[j] += (double)sr[j];
                 dsc[j] += (double)sc[j];
                 sr[j] = sc[j] = 0.f;
             }
         }
+        stage(k0 + 64, (it + 1) & 1);
+        fetch(k0 + 128);
         __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        dsr[j] += (double)sr[j];
+        dsc[j] += (double)sc[j];
     }
 
     // band sums: the 4 pixel quads of a wave, then the 4 waves
@@ -529,8 +544,8 @@ __global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro,
         ++MI;
     }
     const int MJ = MI + m;
-    __shared__ __attribute__((aligned(16))) uint32_t Rt[G::WORDS];
-    __shared__ __attribute__((aligned(16))) uint32_t Ct[G::WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t Rt[2 * G::WORDS];  // two chunk buffers per panel
+    __shared__ __attribute__((aligned(16))) uint32_t Ct[2 * G::WORDS];
     __shared__ float shift_s[128];
     __shared__ double red_s[4 * 128];
     __shared__ double bsum_s[128];
@@ -657,8 +672,8 @@ __device__ __forceinline__ double rsqrt_nr(double x)
 }
 
 // Cholesky and inverse of one 16x16 diagonal block by a single wave.
-// diag_s holds the block (row-major, stride 17) on entry; xt_s receives
-// X = L^{-1} (row-major, stride 17).  Rows of L live in lanes 0..15 and are
+// diag_s holds the block (row-major, stride 17) on entry and L on return; xt_s
+// receives X = L^{-1} (row-major, stride 17).  Rows of L live in lanes 0..15 and are
 // shared with lane broadcasts; the reciprocal pivots are wave-uniform and are
 // reused by the inverse, whose columns are computed by lanes 0..15 from the
 // broadcast rows of L.  Returns 1 if a pivot was not positive.
@@ -687,6 +702,15 @@ __device__ __forceinline__ int factor_diag16(T* diag_s, T* xt_s, int lane)
             if (r >= q) a[q] -= lrk * lqk;
         }
     }
+    // L to LDS (rows in lanes 0..15; diag_s is no longer needed), read back
+    // by every lane with broadcast loads: broadcasting the rows again from
+    // registers would keep all 120 column values live in scalar registers
+    if (lane < 16)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) diag_s[r * 17 + q] = a[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // X = L^{-1}: lane c (= r) computes column c by forward substitution
     T x[16];
 #pragma unroll
@@ -694,7 +718,7 @@ __device__ __forceinline__ int factor_diag16(T* diag_s, T* xt_s, int lane)
         T s0 = (q == r) ? (T)1 : (T)0, s1 = (T)0;
 #pragma unroll
         for (int k = 0; k < q; ++k) {
-            const T lqk = bcast(a[k], q);
+            const T lqk = diag_s[q * 17 + k];
             if (k & 1) s1 -= lqk * x[k];
             else s0 -= lqk * x[k];
         }
