@@ -22,15 +22,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ERX pixels/s + lines/s at 108/224 bands; mixed/batched vs plain FP32 at stated err"
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
-KERNEL_SRC = os.path.join(ROOT, "paper_2408_14947_amd", "csrc", "erx_kernels.hip")
+# sources of the kernels the long-scan workload runs (the traffic record is tied to them)
+KERNEL_SRC = [os.path.join(ROOT, "paper_2408_14947_amd", "csrc", f) for f in ("erx_kernels.hip", "erx_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_long-scan-224.md")
 WORKLOAD = ("long-scan-224: one stream, 20000 lines x 1024 px x 224 bands, f32, momentum 0.1, "
             "ridge 1e-5, drifting 4-endmember mixture, 0.2% 3x3 patches")
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def short_kernel(name):

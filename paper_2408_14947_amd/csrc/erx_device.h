@@ -1,0 +1,217 @@
+// Device helpers shared by the ERX kernels: matrix-core tile products in the
+// accumulator layout, global-memory access, pass descriptors and the
+// single-wave factorisation of a 16x16 block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <type_traits>
+
+#include "erx_internal.h"
+
+namespace erx {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <class T> struct VT;
+template <> struct VT<float> { typedef f4 v; };
+template <> struct VT<double> { typedef d4 v; };
+
+// Row held by lane (g, c), register i, of a 16x16 accumulator tile.  The
+// 16x16x4 FP32 MFMA places row 4g+i there, the FP64 one row 4i+g.  Products
+// X^T Y are layout-agnostic (the contraction runs over every row once), so
+// only code that names rows explicitly uses this.
+template <class T> __device__ __forceinline__ int rowof(int g, int i)
+{
+    return std::is_same<T, double>::value ? 4 * i + g : 4 * g + i;
+}
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// acc += X^T Y for two accumulator-layout tiles held as register quadruples
+template <class V>
+__device__ __forceinline__ V mma_xty(V acc, const V x, const V y)
+{
+    acc = mfma(x[0], y[0], acc);
+    acc = mfma(x[1], y[1], acc);
+    acc = mfma(x[2], y[2], acc);
+    acc = mfma(x[3], y[3], acc);
+    return acc;
+}
+
+// ---------------------------------------------------------------- input loads
+// Pointers that reach a kernel inside the pass descriptors are generic; the
+// memory behind them is always device global memory, and accessing it through
+// global-address-space pointers gives global (not flat) instructions, whose
+// completion is tracked separately from LDS traffic.
+#define GLB __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+// copy of a pass descriptor from global memory (class types cannot be copied
+// out of a global-address-space lvalue directly)
+__device__ __forceinline__ StreamDesc load_desc(const StreamDesc* p)
+{
+    static_assert(sizeof(StreamDesc) % 16 == 0, "descriptor size");
+    u4v w[sizeof(StreamDesc) / 16];
+    const GLB u4v* q = (const GLB u4v*)glb(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(StreamDesc) / 16); ++i) w[i] = q[i];
+    StreamDesc d;
+    __builtin_memcpy(&d, w, sizeof d);
+    return d;
+}
+
+template <int DT> __device__ __forceinline__ float ld1(const void* X, size_t i);
+template <> __device__ __forceinline__ float ld1<DT_F32>(const void* X, size_t i)
+{
+    return glb((const float*)X)[i];
+}
+template <> __device__ __forceinline__ float ld1<DT_F16>(const void* X, size_t i)
+{
+    return __half2float(__ushort_as_half(glb((const unsigned short*)X)[i]));
+}
+template <> __device__ __forceinline__ float ld1<DT_U16>(const void* X, size_t i)
+{
+    return (float)glb((const uint16_t*)X)[i] * (1.0f / 65536.0f);  // exact
+}
+
+template <int DT> __device__ __forceinline__ const void* advance(const void* x, size_t elems)
+{
+    return (const char*)x + elems * (DT == DT_F32 ? 4 : 2);
+}
+
+// the stream owning pass line `line` (streams are stored in line order)
+__device__ __forceinline__ StreamDesc stream_of_line(const Pass& P, int line)
+{
+    if (!P.sd) return P.one;
+    const GLB StreamDesc* sd = glb(P.sd);
+    int lo = 0, hi = P.nstreams - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sd[mid].line0 <= line) lo = mid;
+        else hi = mid - 1;
+    }
+    return load_desc(P.sd + lo);
+}
+
+// the stream owning pass scan segment `g`
+__device__ __forceinline__ StreamDesc stream_of_seg(const Pass& P, int g)
+{
+    if (!P.sd) return P.one;
+    const GLB StreamDesc* sd = glb(P.sd);
+    int lo = 0, hi = P.nstreams - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sd[mid].seg0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return load_desc(P.sd + lo);
+}
+
+__device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile I <= J
+{
+    return (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
+}
+
+__device__ __forceinline__ int tile_lc(int J, int K, int NT)  // lower tile J >= K, column-major
+{
+    return K * NT - K * (K - 1) / 2 + (J - K);
+}
+
+__device__ __forceinline__ float bcast(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double bcast(double v, int l)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/sqrt(x): the hardware estimate, refined by Newton steps (two for FP64,
+// giving close to full double precision; one for FP32).
+__device__ __forceinline__ float rsqrt_nr(float x)
+{
+    float y = __builtin_amdgcn_rsqf(x);
+    return y * (1.5f - 0.5f * x * y * y);
+}
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
+// Cholesky and inverse of one 16x16 diagonal block by a single wave.
+// diag_s holds the block (row-major, stride 17) on entry and L on return; xt_s
+// receives X = L^{-1} (row-major, stride 17).  Rows of L live in lanes 0..15 and are
+// shared with lane broadcasts; the reciprocal pivots are wave-uniform and are
+// reused by the inverse, whose columns are computed by lanes 0..15 from the
+// broadcast rows of L.  Returns 1 if a pivot was not positive.
+template <class T>
+__device__ __forceinline__ int factor_diag16(T* diag_s, T* xt_s, int lane)
+{
+    const int r = lane & 15;
+    int bad = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T a[16], invd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = (q <= r) ? diag_s[r * 17 + q] : (T)0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const T akk = bcast(a[k], k);
+        if (!(akk > (T)0) && !(akk != akk)) bad = 1;  // a NaN pivot propagates, it is not "not PD"
+        const T inv = rsqrt_nr(akk);
+        invd[k] = inv;
+        const T lrk = (r > k) ? a[k] * inv : ((r == k) ? akk * inv : (T)0);
+        a[k] = lrk;
+#pragma unroll
+        for (int q = k + 1; q < 16; ++q) {
+            const T lqk = bcast(lrk, q);
+            if (r >= q) a[q] -= lrk * lqk;
+        }
+    }
+    // L to LDS (rows in lanes 0..15; diag_s is no longer needed), read back
+    // by every lane with broadcast loads: broadcasting the rows again from
+    // registers would keep all 120 column values live in scalar registers
+    if (lane < 16)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) diag_s[r * 17 + q] = a[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // X = L^{-1}: lane c (= r) computes column c by forward substitution
+    T x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        T s0 = (q == r) ? (T)1 : (T)0, s1 = (T)0;
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            const T lqk = diag_s[q * 17 + k];
+            if (k & 1) s1 -= lqk * x[k];
+            else s0 -= lqk * x[k];
+        }
+        x[q] = (s0 + s1) * invd[q];
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xt_s[q * 17 + lane] = x[q];  // xt[row][col] = X[row][col]
+    return bad;
+}
+
+}  // namespace erx

@@ -17,131 +17,9 @@
 // layout four MFMAs whose A and B operands are register i of two such tiles
 // X and Y compute X^T Y (in the same layout), so tiles produced by one
 // product feed the next without any data movement.
-#include <hip/hip_runtime.h>
-#include <hip/hip_fp16.h>
-#include <stdint.h>
-#include <type_traits>
-
-#include "erx_internal.h"
+#include "erx_device.h"
 
 namespace erx {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-template <class T> struct VT;
-template <> struct VT<float> { typedef f4 v; };
-template <> struct VT<double> { typedef d4 v; };
-
-// Row held by lane (g, c), register i, of a 16x16 accumulator tile.  The
-// 16x16x4 FP32 MFMA places row 4g+i there, the FP64 one row 4i+g.  Products
-// X^T Y are layout-agnostic (the contraction runs over every row once), so
-// only code that names rows explicitly uses this.
-template <class T> __device__ __forceinline__ int rowof(int g, int i)
-{
-    return std::is_same<T, double>::value ? 4 * i + g : 4 * g + i;
-}
-
-__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// acc += X^T Y for two accumulator-layout tiles held as register quadruples
-template <class V>
-__device__ __forceinline__ V mma_xty(V acc, const V x, const V y)
-{
-    acc = mfma(x[0], y[0], acc);
-    acc = mfma(x[1], y[1], acc);
-    acc = mfma(x[2], y[2], acc);
-    acc = mfma(x[3], y[3], acc);
-    return acc;
-}
-
-// ---------------------------------------------------------------- input loads
-// Pointers that reach a kernel inside the pass descriptors are generic; the
-// memory behind them is always device global memory, and accessing it through
-// global-address-space pointers gives global (not flat) instructions, whose
-// completion is tracked separately from LDS traffic.
-#define GLB __attribute__((address_space(1)))
-template <class T> __device__ __forceinline__ GLB T* glb(T* p) { return (GLB T*)p; }
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
-typedef unsigned u4v __attribute__((ext_vector_type(4)));
-
-// copy of a pass descriptor from global memory (class types cannot be copied
-// out of a global-address-space lvalue directly)
-__device__ __forceinline__ StreamDesc load_desc(const StreamDesc* p)
-{
-    static_assert(sizeof(StreamDesc) % 16 == 0, "descriptor size");
-    u4v w[sizeof(StreamDesc) / 16];
-    const GLB u4v* q = (const GLB u4v*)glb(p);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(StreamDesc) / 16); ++i) w[i] = q[i];
-    StreamDesc d;
-    __builtin_memcpy(&d, w, sizeof d);
-    return d;
-}
-
-template <int DT> __device__ __forceinline__ float ld1(const void* X, size_t i);
-template <> __device__ __forceinline__ float ld1<DT_F32>(const void* X, size_t i)
-{
-    return glb((const float*)X)[i];
-}
-template <> __device__ __forceinline__ float ld1<DT_F16>(const void* X, size_t i)
-{
-    return __half2float(__ushort_as_half(glb((const unsigned short*)X)[i]));
-}
-template <> __device__ __forceinline__ float ld1<DT_U16>(const void* X, size_t i)
-{
-    return (float)glb((const uint16_t*)X)[i] * (1.0f / 65536.0f);  // exact
-}
-
-template <int DT> __device__ __forceinline__ const void* advance(const void* x, size_t elems)
-{
-    return (const char*)x + elems * (DT == DT_F32 ? 4 : 2);
-}
-
-// the stream owning pass line `line` (streams are stored in line order)
-__device__ __forceinline__ StreamDesc stream_of_line(const Pass& P, int line)
-{
-    if (!P.sd) return P.one;
-    const GLB StreamDesc* sd = glb(P.sd);
-    int lo = 0, hi = P.nstreams - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sd[mid].line0 <= line) lo = mid;
-        else hi = mid - 1;
-    }
-    return load_desc(P.sd + lo);
-}
-
-// the stream owning pass scan segment `g`
-__device__ __forceinline__ StreamDesc stream_of_seg(const Pass& P, int g)
-{
-    if (!P.sd) return P.one;
-    const GLB StreamDesc* sd = glb(P.sd);
-    int lo = 0, hi = P.nstreams - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sd[mid].seg0 <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return load_desc(P.sd + lo);
-}
-
-__device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile I <= J
-{
-    return (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
-}
-
-__device__ __forceinline__ int tile_lc(int J, int K, int NT)  // lower tile J >= K, column-major
-{
-    return K * NT - K * (K - 1) / 2 + (J - K);
-}
 
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -644,92 +522,6 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
 // re-factors only those lines.  Output: M^T tiles (FP32, accumulator layout,
 // the operand form the score kernel needs), mu_t (FP32), flags, estimate.
 // ============================================================================
-__device__ __forceinline__ float bcast(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-__device__ __forceinline__ double bcast(double v, int l)
-{
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
-    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// 1/sqrt(x): the hardware estimate, refined by Newton steps (two for FP64,
-// giving close to full double precision; one for FP32).
-__device__ __forceinline__ float rsqrt_nr(float x)
-{
-    float y = __builtin_amdgcn_rsqf(x);
-    return y * (1.5f - 0.5f * x * y * y);
-}
-__device__ __forceinline__ double rsqrt_nr(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
-    return y;
-}
-
-// Cholesky and inverse of one 16x16 diagonal block by a single wave.
-// diag_s holds the block (row-major, stride 17) on entry and L on return; xt_s
-// receives X = L^{-1} (row-major, stride 17).  Rows of L live in lanes 0..15 and are
-// shared with lane broadcasts; the reciprocal pivots are wave-uniform and are
-// reused by the inverse, whose columns are computed by lanes 0..15 from the
-// broadcast rows of L.  Returns 1 if a pivot was not positive.
-template <class T>
-__device__ __forceinline__ int factor_diag16(T* diag_s, T* xt_s, int lane)
-{
-    const int r = lane & 15;
-    int bad = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    T a[16], invd[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) a[q] = (q <= r) ? diag_s[r * 17 + q] : (T)0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const T akk = bcast(a[k], k);
-        if (!(akk > (T)0) && !(akk != akk)) bad = 1;  // a NaN pivot propagates, it is not "not PD"
-        const T inv = rsqrt_nr(akk);
-        invd[k] = inv;
-        const T lrk = (r > k) ? a[k] * inv : ((r == k) ? akk * inv : (T)0);
-        a[k] = lrk;
-#pragma unroll
-        for (int q = k + 1; q < 16; ++q) {
-            const T lqk = bcast(lrk, q);
-            if (r >= q) a[q] -= lrk * lqk;
-        }
-    }
-    // L to LDS (rows in lanes 0..15; diag_s is no longer needed), read back
-    // by every lane with broadcast loads: broadcasting the rows again from
-    // registers would keep all 120 column values live in scalar registers
-    if (lane < 16)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) diag_s[r * 17 + q] = a[q];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // X = L^{-1}: lane c (= r) computes column c by forward substitution
-    T x[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        T s0 = (q == r) ? (T)1 : (T)0, s1 = (T)0;
-#pragma unroll
-        for (int k = 0; k < q; ++k) {
-            const T lqk = diag_s[q * 17 + k];
-            if (k & 1) s1 -= lqk * x[k];
-            else s0 -= lqk * x[k];
-        }
-        x[q] = (s0 + s1) * invd[q];
-    }
-    if (lane < 16)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) xt_s[q * 17 + lane] = x[q];  // xt[row][col] = X[row][col]
-    return bad;
-}
-
 template <int NT> struct CholLds {
     float part[NT * (NT + 1) / 2 * 32];  // per-tile partial sums (norms, mat-vecs)
     float vec[4][16 * NT];                // x, y, z, scratch vectors
@@ -1238,304 +1030,6 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
 }
 
 // ============================================================================
-// Small band counts (b <= 16, one 16-band tile): the whole method fused, with
-// the moving-average recurrence kept on chip (Sec. III-C to III-E).
-//
-// One workgroup (4 waves) per stream walks that stream's lines in order:
-//   Gram    wave w takes 16-pixel tiles w, w+4, ...; a tile (lane (g, c):
-//           pixels 4g..4g+3 of band c) gives X^T X in four FP64 MFMAs.  Each
-//           wave shifts its values by the first pixel of its first tile, in
-//           FP64, so the products and sums are exact for every storage type
-//           (an FP32 Gram would lose up to kappa * 2^-24 on the ill-conditioned
-//           backgrounds of lines with fewer pixels than bands; here the cost is
-//           small); the four waves' shifted sums are combined exactly.
-//   EMA     wave 0 holds K_t and mu_t in FP64 registers (the state layout).
-//   Factor  wave 0: K_t + eps I (padded bands: identity), Cholesky and
-//           inverse of the 16 x 16 block in FP64.
-//   Score   Y = L^{-1} R for 16-pixel tiles (four FP32 MFMAs), delta = ||y||.
-//   Norm    optional per-line standardisation of the scores.
-// The line is read from global memory twice (statistics, then scores); the
-// second read comes from L2.  Every line is factored in FP64 (counted as an
-// FP64 factorisation); lines whose block is not positive definite score NaN.
-// ============================================================================
-// Loads are issued in batches of SB tiles per wave (one: more batches in
-// flight per wave would cost a wave per SIMD), the next batch in flight
-// while the current one is multiplied, and the first batch of the next phase
-// (the scores of this line, the Gram of the next line) is issued before the
-// barrier that precedes it.  All loads are unconditional (clamped addresses,
-// values masked where used).
-constexpr int SB = 1;
-
-// Raw storage values, converted to FP32 only where they are used (a
-// conversion right after a load would make the compiler wait for it).
-template <int DT> struct Raw1 {
-    typedef unsigned short T;
-    static __device__ __forceinline__ T ld(const void* X, size_t i) { return glb((const unsigned short*)X)[i]; }
-    static __device__ __forceinline__ float cvt(T v)
-    {
-        return DT == DT_F16 ? __half2float(__ushort_as_half(v)) : (float)v * (1.0f / 65536.0f);
-    }
-};
-template <> struct Raw1<DT_F32> {
-    typedef float T;
-    static __device__ __forceinline__ T ld(const void* X, size_t i) { return glb((const float*)X)[i]; }
-    static __device__ __forceinline__ float cvt(T v) { return v; }
-};
-// four consecutive elements [i, i+4): one vector load with VEC, else element
-// loads of the first `left` ones (offset clamped to 0 for the rest)
-template <int DT, bool VEC> struct Raw4 {
-    typename Raw1<DT>::T e[4];
-    __device__ __forceinline__ void ld(const void* X, size_t i, int left)
-    {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) e[q] = Raw1<DT>::ld(X, q < left ? i + q : 0);
-    }
-    __device__ __forceinline__ f4 cvt() const
-    {
-        return f4{Raw1<DT>::cvt(e[0]), Raw1<DT>::cvt(e[1]), Raw1<DT>::cvt(e[2]), Raw1<DT>::cvt(e[3])};
-    }
-};
-template <> struct Raw4<DT_F32, true> {
-    f4 v;
-    __device__ __forceinline__ void ld(const void* X, size_t i, int) { v = *(const GLB f4*)glb((const float*)X + i); }
-    __device__ __forceinline__ f4 cvt() const { return v; }
-};
-template <int DT> struct Raw4H {
-    u2v v;
-    __device__ __forceinline__ void ld(const void* X, size_t i, int)
-    {
-        v = *(const GLB u2v*)glb((const unsigned short*)X + i);
-    }
-    __device__ __forceinline__ f4 cvt() const
-    {
-        return f4{Raw1<DT>::cvt((unsigned short)(v.x & 0xffffu)), Raw1<DT>::cvt((unsigned short)(v.x >> 16)),
-                  Raw1<DT>::cvt((unsigned short)(v.y & 0xffffu)), Raw1<DT>::cvt((unsigned short)(v.y >> 16))};
-    }
-};
-template <> struct Raw4<DT_F16, true> : Raw4H<DT_F16> {};
-template <> struct Raw4<DT_U16, true> : Raw4H<DT_U16> {};
-
-template <int DT, bool VEC>
-__global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsigned long long* __restrict__ ctr)
-{
-    const int sidx = blockIdx.x;
-    if (sidx >= P.nstreams) return;  // uniform for the workgroup
-    const StreamDesc d = P.sd ? load_desc(P.sd + sidx) : P.one;
-    const int p = d.p, b = d.b;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
-    __shared__ double red_s[4][256 + 16];
-    __shared__ double diag_s[16 * 17];
-    __shared__ double xt_s[16 * 17];
-    __shared__ double nrm_s[4][2];
-    __shared__ double wsh_s[4][16];
-    __shared__ float mu_s[16];
-    __shared__ int wn_s[4];
-    __shared__ int bad_s;
-
-    GLB double* state = glb(d.state);
-    double Kst[4] = {0.0, 0.0, 0.0, 0.0}, mst = 0.0;  // wave 0: K (state layout) and mu of band c
-    if (w == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) Kst[i] = state[lane * 4 + i];
-        mst = state[256 + c];
-    }
-    const int ntile = (p + 15) >> 4;
-    const int ntw = ntile > w ? (ntile - w + 3) >> 2 : 0;  // tiles of this wave: w, w+4, ...
-    const int nbat = (ntw + SB - 1) / SB;
-    const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
-    const size_t line_elems = (size_t)p * b;
-    const int band0 = 4 * g;
-
-    // Gram operands: lane (g, c) holds pixels 4g..4g+3 of band c of a tile
-    typedef typename Raw1<DT>::T RT;
-    auto gload = [&](const void* X, int j, RT (&buf)[SB][4]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int tt = w + 4 * (SB * j + u);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int px = 16 * tt + 4 * g + i;
-                const bool ok = px < p && c < b;
-                buf[u][i] = Raw1<DT>::ld(X, ok ? (size_t)px * b + c : 0);
-            }
-        }
-    };
-    // score operands: lane (g, c) holds bands 4g..4g+3 of pixel c of a tile
-    auto sload = [&](const void* X, int j, Raw4<DT, VEC> (&buf)[SB]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int tt = w + 4 * (SB * j + u);
-            const int px = 16 * tt + c;
-            const bool okl = px < p && band0 < b;
-            buf[u].ld(X, okl ? (size_t)px * b + band0 : 0, okl ? b - band0 : 0);
-        }
-    };
-
-    RT ga[SB][4], gb[SB][4];
-    Raw4<DT, VEC> sa[SB], sb[SB];
-    if (d.n > 0) gload(d.x, 0, ga);
-    long long t = d.t0;
-    for (int l = 0; l < d.n; ++l, ++t) {
-        const void* X = advance<DT>(d.x, (size_t)l * line_elems);
-        GLB float* out = glb(d.out + (size_t)l * p);
-
-        // ---- Gram of this wave's tiles, shifted by the first pixel of the wave's
-        //      first tile (a value of this line, so the sums stay well scaled).
-        //      Differences in FP64 and FP64 products: exact for the storage types.
-        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-        double bsd = 0.0;
-        const double sh = (double)__shfl(Raw1<DT>::cvt(ga[0][0]), c);  // pixel 16w, band c (lane c holds it)
-        for (int j = 0; j < nbat; ++j) {
-            gload(X, j + 1, gb);  // next batch (clamped past the end)
-#pragma unroll
-            for (int u = 0; u < SB; ++u) {
-                const int tt = w + 4 * (SB * j + u);
-                d4 xv;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int px = 16 * tt + 4 * g + i;
-                    xv[i] = (px < p && c < b) ? (double)Raw1<DT>::cvt(ga[u][i]) - sh : 0.0;
-                }
-                bsd += (xv[0] + xv[1]) + (xv[2] + xv[3]);
-                acc = mma_xty(acc, xv, xv);
-            }
-#pragma unroll
-            for (int u = 0; u < SB; ++u)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) ga[u][i] = gb[u][i];
-        }
-        bsd += __shfl_xor(bsd, 16);
-        bsd += __shfl_xor(bsd, 32);
-        // FP64 accumulator layout: register i of lane (g, c) is row 4i+g, column c
-#pragma unroll
-        for (int i = 0; i < 4; ++i) red_s[w][(4 * i + g) * 16 + c] = acc[i];
-        if (g == 0) {
-            red_s[w][256 + c] = bsd;
-            wsh_s[w][c] = ntw ? sh : 0.0;
-        }
-        // pixels of this wave: 16 per tile, less the shortfall of the last tile if it is this wave's
-        if (lane == 0) wn_s[w] = ntw ? 16 * ntw - (((ntile - 1 - w) & 3) == 0 ? 16 * ntile - p : 0) : 0;
-        sload(X, 0, sa);  // first score batch, in flight during the factorisation
-        __syncthreads();
-
-        // ---- line statistics, moving averages and factorisation (wave 0).
-        //      The per-wave sums (shift s_w, n_w pixels, B_w = sum(x - s_w),
-        //      S_w = sum (x - s_w)(x - s_w)^T) combine exactly:
-        //      m_w = s_w + B_w / n_w, m = sum n_w m_w / p,
-        //      C = sum_w [S_w - B_w B_w^T / n_w + n_w (m_w - m)(m_w - m)^T].
-        if (w == 0) {
-            const double a = (t == 0) ? 1.0 : d.alpha;
-            double mw_c[4], m_c = 0.0;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int nw = wn_s[v];
-                mw_c[v] = nw ? wsh_s[v][c] + red_s[v][256 + c] / nw : 0.0;
-                m_c += nw * mw_c[v];
-            }
-            m_c *= inv_p;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 4 * g + i;
-                double cs = 0.0, m_r = 0.0, mw_r[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int nw = wn_s[v];
-                    mw_r[v] = nw ? wsh_s[v][row] + red_s[v][256 + row] / nw : 0.0;
-                    m_r += nw * mw_r[v];
-                }
-                m_r *= inv_p;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int nw = wn_s[v];
-                    if (nw == 0) continue;
-                    cs += red_s[v][row * 16 + c] - red_s[v][256 + row] * red_s[v][256 + c] / nw +
-                          nw * (mw_r[v] - m_r) * (mw_c[v] - m_c);
-                }
-                const double kh = cs * inv_p1;
-                Kst[i] = (1.0 - a) * Kst[i] + a * kh;
-                double av = Kst[i];
-                if (row >= b || c >= b) av = (row == c) ? 1.0 : 0.0;
-                else if (row == c) av += d.eps;
-                diag_s[row * 17 + c] = av;
-            }
-            const double muh = (c < b) ? m_c : 0.0;
-            mst = (1.0 - a) * mst + a * muh;
-            if (lane < 16) mu_s[lane] = (float)mst;
-            const int bad = factor_diag16(diag_s, xt_s, lane);
-            if (lane == 0) {
-                bad_s = bad;
-                atomicAdd(&ctr[0], 1ull);
-                if (bad) atomicAdd(&ctr[1], 1ull);
-            }
-        }
-        __syncthreads();
-
-        // ---- scores
-        const bool bad = bad_s != 0;
-        f4 xt, m4;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            xt[i] = (float)xt_s[c * 17 + 4 * g + i];  // X^T[4g+i][c]
-            m4[i] = mu_s[4 * g + i];
-        }
-        double s1 = 0.0, s2 = 0.0;
-        const void* Xn = advance<DT>(d.x, (size_t)(l + 1 < d.n ? l + 1 : l) * line_elems);
-        for (int j = 0; j < nbat; ++j) {
-            if (j + 1 < nbat) sload(X, j + 1, sb);
-            else gload(Xn, 0, ga);  // the next line's first Gram batch
-#pragma unroll
-            for (int u = 0; u < SB; ++u) {
-                const int tt = w + 4 * (SB * j + u);
-                const int px = 16 * tt + c;
-                const bool okp = px < p;
-                f4 r;
-                const f4 xr = sa[u].cvt();
-#pragma unroll
-                for (int q = 0; q < 4; ++q) r[q] = (okp && band0 + q < b) ? xr[q] - m4[q] : 0.f;
-                const f4 y = mma_xty(f4{0.f, 0.f, 0.f, 0.f}, xt, r);  // L^{-1} r of pixel c, rows 4g..4g+3
-                float ss = (y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]);
-                ss += __shfl_xor(ss, 16);
-                ss += __shfl_xor(ss, 32);
-                const float dl = bad ? __builtin_nanf("") : sqrtf(ss);
-                if (g == 0 && okp) {
-                    out[px] = dl;
-                    s1 += (double)dl;
-                    s2 += (double)dl * (double)dl;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < SB; ++u) sa[u] = sb[u];
-        }
-        if (nbat == 0) gload(Xn, 0, ga);
-        if (normalise && d.outn) {
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                s1 += __shfl_xor(s1, o);
-                s2 += __shfl_xor(s2, o);
-            }
-            if (lane == 0) {
-                nrm_s[w][0] = s1;
-                nrm_s[w][1] = s2;
-            }
-            __syncthreads();
-            const double m1 = (nrm_s[0][0] + nrm_s[1][0] + nrm_s[2][0] + nrm_s[3][0]) * inv_p;
-            const double m2 = (nrm_s[0][1] + nrm_s[1][1] + nrm_s[2][1] + nrm_s[3][1]) * inv_p;
-            const double var = m2 - m1 * m1;
-            const double sd = var > 0.0 ? sqrt(var) : 0.0;
-            GLB float* outn = glb(d.outn + (size_t)l * p);
-            for (int px = tid; px < p; px += 256)
-                outn[px] = sd > 0.0 ? (float)(((double)out[px] - m1) / sd) : 0.f;
-        }
-        __syncthreads();
-    }
-    if (w == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) state[lane * 4 + i] = Kst[i];
-        if (lane < 16) state[256 + lane] = mst;
-    }
-}
-
-// ============================================================================
 // Line normalisation (Sec. III-E, Eq. (24)): population mean and deviation of
 // the p scores of each line in FP64, (delta - mean) / std, 0 when std is 0.
 // ============================================================================
@@ -1861,21 +1355,6 @@ hipError_t launch_sproj(const float* X, long long npx, int b, const __half* W16,
 hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gram1x, dim3((unsigned)P.nlines), dim3(256), 0, s, P, stats, stat_entries(1));
-    return hipGetLastError();
-}
-
-hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s)
-{
-    const dim3 grid((unsigned)P.nstreams), block(256);
-#define ERX_SMALL(DTV)                                                                                      \
-    if (P.vec4) hipLaunchKernelGGL((k_small<DTV, true>), grid, block, 0, s, P, normalise, ctr);            \
-    else hipLaunchKernelGGL((k_small<DTV, false>), grid, block, 0, s, P, normalise, ctr);
-    switch (dtype) {
-    case DT_F32: ERX_SMALL(DT_F32) break;
-    case DT_F16: ERX_SMALL(DT_F16) break;
-    default: ERX_SMALL(DT_U16) break;
-    }
-#undef ERX_SMALL
     return hipGetLastError();
 }
 
