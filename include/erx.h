@@ -185,10 +185,13 @@ ERX_API int erx_batch_stats(erx_batch *bt, erx_stats_t *out);
 ERX_API int erx_batch_use_graphs(erx_batch *bt, int on);
 /* Streams with at most 16 bands can run on a fused path: one workgroup per stream walks the
  * stream's lines in order with the moving-average state on chip (no per-line statistics in
- * device memory, no scan), every line factored in FP64 and the Gram in FP32 whatever the
- * configured precision.  mode 1: use it for every such stream; 0: never; -1 (default): when
- * at least 32 such streams are in the batch.  Results agree with the general path to
- * rounding.  ERX_EINVAL for another mode. */
+ * device memory, no scan), the Gram from FP64 differences and products and every line
+ * factored in FP64, whatever the configured precision.  The line is held in LDS (one read
+ * from device memory, the next line's loads in flight meanwhile) when every line of the
+ * push is at most 40960 bytes and starts on a 16-byte boundary; otherwise each tile is
+ * streamed from device memory twice.  mode 1: use it for every such stream; 2: the same
+ * but always streamed; 0: never; -1 (default): when at least 32 such streams are in the
+ * batch.  Results agree with the general path to rounding.  ERX_EINVAL for another mode. */
 ERX_API int erx_batch_small_path(erx_batch *bt, int mode);
 ERX_API int erx_batch_synchronize(erx_batch *bt);
 ERX_API void erx_batch_destroy(erx_batch *bt);

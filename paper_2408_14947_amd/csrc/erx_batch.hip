@@ -71,7 +71,7 @@ struct erx_batch {
     hipStream_t own_stream = nullptr;
     unsigned long long* ctr = nullptr;
     bool use_graphs = true;
-    int small_mode = -1;  // fused path for one-tile streams: -1 auto, 0 off, 1 on
+    int small_mode = -1;  // fused path for one-tile streams: -1 auto, 0 off, 1 on, 2 on (streamed variant)
     unsigned long long notpd_before = 0;
 };
 
@@ -224,7 +224,7 @@ int erx_batch_use_graphs(erx_batch* bt, int on)
 int erx_batch_small_path(erx_batch* bt, int mode)
 {
     if (!bt) return fail(ERX_EINVAL, "NULL batch");
-    if (mode < -1 || mode > 1) return fail(ERX_EINVAL, "small-path mode must be -1, 0 or 1");
+    if (mode < -1 || mode > 2) return fail(ERX_EINVAL, "small-path mode must be -1, 0, 1 or 2");
     bt->small_mode = mode;
     return ERX_OK;
 }
@@ -278,13 +278,13 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
     const int C = c.block_lines, seg = c.scan_lines;
 
     for (Group& g : bt->groups) {
-        if (g.NT == 1 && (bt->small_mode == 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
+        if (g.NT == 1 && (bt->small_mode >= 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
             // fused path: one launch, every stream's lines in order
             const int slot = g.next_slot;
             g.next_slot = (g.next_slot + 1) % NSLOT;
             HIPCHK(hipEventSynchronize(g.slot_ev[slot]));
             StreamDesc* hd = g.h_sd[slot];
-            int nsd = 0, vec4 = 1, pmax = 0;
+            int nsd = 0, vec4 = 1, pmax = 0, lmax = 0, al16 = bt->small_mode != 2;
             for (int s : g.streams) {
                 if (nlines[s] == 0) continue;
                 BStream& B = bt->st[s];
@@ -302,6 +302,9 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
                 hd[nsd++] = d;
                 vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)lines[s] % (4 * esz)) == 0;
                 pmax = std::max(pmax, B.p);
+                const long long lb = (long long)B.p * B.b * esz;  // bytes of one line
+                al16 = al16 && lb % 16 == 0 && (uintptr_t)lines[s] % 16 == 0;
+                lmax = (int)std::min<long long>(std::max<long long>(lmax, lb), 1LL << 30);
                 B.t += nlines[s];
             }
             if (nsd > 0) {
@@ -312,7 +315,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
                 P.vec4 = vec4;
                 HIPCHK(hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
                                       bt->stream));
-                HIPCHK(launch_small(c.dtype, P, c.normalise, bt->ctr, bt->stream));
+                HIPCHK(launch_small(c.dtype, P, c.normalise, bt->ctr, al16 ? lmax : 0, bt->stream));
             }
             HIPCHK(hipEventRecord(g.slot_ev[slot], bt->stream));
             continue;

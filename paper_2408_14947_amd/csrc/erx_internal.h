@@ -63,8 +63,12 @@ hipError_t launch_sproj(const float* X, long long npx, int b, const __half* W16,
 // exact (FP64) statistics of one-tile FP32 streams, in the k_gram layout
 hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s);
 // fused path for streams with at most 16 bands: one workgroup per stream, its
-// n lines in order, state read from and written back to StreamDesc::state
-hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s);
+// n lines in order, state read from and written back to StreamDesc::state.
+// lds_line_bytes > 0 (the largest line of the pass, every line starting on a
+// 16-byte boundary) selects the variant that holds the line in LDS when it fits;
+// 0 selects the variant that streams every tile from global memory.
+hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, int lds_line_bytes,
+                        hipStream_t s);
 hipError_t launch_labels(const float* dn, int n, int p, float tau, long long t0, int warmup,
                          unsigned char* out, hipStream_t s);
 

@@ -935,7 +935,12 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
     constexpr int NTL = NT * (NT + 1) / 2;
     constexpr int PT = SCORE_PT;
     constexpr int MR = (NT * 64 + 255) / 256;  // float4 per thread to stage the longest column
-    const int line = blockIdx.x / ngrp, grp = blockIdx.x - line * ngrp;
+    // Workgroups are dispatched to the 8 XCDs round robin (bid mod 8), each with
+    // its own L2: all pixel groups of a line go to one XCD, one after another in
+    // its dispatch order, so the line's M tiles are fetched into one L2 once.
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int lx = j / ngrp, grp = j - lx * ngrp;
+    const int line = lx * 8 + xcd;
     if (line >= P.nlines) return;  // uniform for the workgroup
     const StreamDesc d = stream_of_line(P, line);
     const int p = d.p, b = d.b;
@@ -1181,7 +1186,7 @@ static void score_one(const Pass& P, const float* Mt, const float* mu32, hipStre
 {
     const int per = 4 * SCORE_PT * 16;
     const int ngrp = (P.pmax + per - 1) / per;
-    const dim3 grid((unsigned)((long long)P.nlines * ngrp));
+    const dim3 grid((unsigned)((long long)(P.nlines + 7) / 8 * 8 * ngrp));
     if (P.vec4) hipLaunchKernelGGL((k_score<NT, DT, true>), grid, dim3(256), 0, s, P, Mt, mu32, ngrp);
     else hipLaunchKernelGGL((k_score<NT, DT, false>), grid, dim3(256), 0, s, P, Mt, mu32, ngrp);
 }

@@ -83,6 +83,76 @@ template <int DT> struct Raw4H {
 template <> struct Raw4<DT_F16, true> : Raw4H<DT_F16> {};
 template <> struct Raw4<DT_U16, true> : Raw4H<DT_U16> {};
 
+// Cholesky factor L of a 16x16 FP64 block A and its inverse X = L^{-1}, by one
+// wave holding both in the state layout (lane (g, c), register i: row 4g+i,
+// column c): four values per lane, so the factorisation costs the kernel few
+// registers.  Right-looking: at step k the pivot comes from lane (k/4, k), the
+// rows of column k from lane (g, k) of each lane's own row group (a DPP row
+// broadcast), and entry
+// (c, k) from lane (k/4, c) through the symmetry of the trailing block (both
+// triangles are updated).  Row k of X is eliminated in the same step: it needs
+// only column k of L and the rows of X above it, which are final by then.
+// On entry a holds A (both triangles); on return a holds L (zero above the
+// diagonal) and x holds X.  When rows and columns nb..15 of A are those of the
+// identity (padded bands) the steps from nb on change nothing and are skipped.
+// Returns 1 if a pivot was not positive (a NaN pivot propagates and is not
+// counted).
+// value of lane K of each row of 16 lanes (DPP row_newbcast), for an FP64 value
+template <int K> __device__ __forceinline__ double row_bcast(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), 0x150 + K, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0x150 + K, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int K>
+__device__ __forceinline__ void factor16_step(double (&a)[4], double (&x)[4], int g, int c, int& bad)
+{
+    constexpr int kg = K >> 2, ki = K & 3;
+    double ar[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ar[i] = row_bcast<K>(a[i]);  // A[4g+i][K]: lane K of the lane's row
+    const double ac = __shfl(a[ki], 16 * kg + c);           // A[K][c] = A[c][K]
+    const double akk = bcast(a[ki], 16 * kg + K);
+    if (!(akk > 0.0) && !(akk != akk)) bad = 1;
+    const double inv = rsqrt_nr(akk);
+    double lr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * g + i;
+        lr[i] = r > K ? ar[i] * inv : (r == K ? akk * inv : 0.0);  // L[r][K]
+    }
+    const double lc = c > K ? ac * inv : 0.0;                      // L[c][K] below the pivot
+    if (g == kg) x[ki] *= inv;                                     // row K of X is final
+    const double xk = __shfl(x[ki], 16 * kg + c);                  // X[K][c]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * g + i;
+        if (c == K) a[i] = lr[i];
+        else if (r > K && c > K) a[i] -= lr[i] * lc;
+        if (r > K) x[i] -= lr[i] * xk;
+    }
+}
+
+template <int... Ks>
+__device__ __forceinline__ void factor16_steps(std::integer_sequence<int, Ks...>, double (&a)[4], double (&x)[4],
+                                               int g, int c, int nb, int& bad)
+{
+    // rows and columns from nb on are the identity and stay so
+    ((Ks < nb ? factor16_step<Ks>(a, x, g, c, bad) : void()), ...);
+}
+
+__device__ __forceinline__ int factor16(double (&a)[4], double (&x)[4], int lane, int nb = 16)
+{
+    const int g = lane >> 4, c = lane & 15;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = (4 * g + i == c) ? 1.0 : 0.0;
+    factor16_steps(std::make_integer_sequence<int, 16>(), a, x, g, c, nb, bad);
+    return bad;
+}
+
 template <int DT, bool VEC>
 __global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsigned long long* __restrict__ ctr)
 {
@@ -92,7 +162,6 @@ __global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsi
     const int p = d.p, b = d.b;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
     __shared__ double red_s[4][256 + 16];
-    __shared__ double diag_s[16 * 17];
     __shared__ double xt_s[16 * 17];
     __shared__ double nrm_s[4][2];
     __shared__ double wsh_s[4][16];
@@ -201,6 +270,7 @@ __global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsi
                 m_c += nw * mw_c[v];
             }
             m_c *= inv_p;
+            double aa[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 4 * g + i;
@@ -224,12 +294,15 @@ __global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsi
                 double av = Kst[i];
                 if (row >= b || c >= b) av = (row == c) ? 1.0 : 0.0;
                 else if (row == c) av += d.eps;
-                diag_s[row * 17 + c] = av;
+                aa[i] = av;
             }
             const double muh = (c < b) ? m_c : 0.0;
             mst = (1.0 - a) * mst + a * muh;
             if (lane < 16) mu_s[lane] = (float)mst;
-            const int bad = factor_diag16(diag_s, xt_s, lane);
+            double xx[4];
+            const int bad = factor16(aa, xx, lane, b);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xt_s[(4 * g + i) * 17 + c] = xx[i];  // X[4g+i][c]
             if (lane == 0) {
                 bad_s = bad;
                 atomicAdd(&ctr[0], 1ull);
@@ -304,8 +377,280 @@ __global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsi
 }
 
 
-hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s)
+// ============================================================================
+// The same fused method with the line held in LDS, for passes whose lines fit
+// the buffer and start on 16-byte boundaries.  Each thread keeps NR 16-byte
+// words of the NEXT line in registers: their loads are issued as soon as the
+// current line has been copied to LDS and complete while it is processed, so
+// a line costs one memory round trip that overlaps the previous line's work
+// instead of one per tile.  The Gram and the scores both read the line from
+// LDS in the layout their MFMA operands need (a tile transposes between the
+// two), so the line is read from global memory once.
+//
+// The Gram shift is the line's first pixel, common to the four waves, so their
+// FP64 sums S = sum (x - s)(x - s)^T and B = sum (x - s) add directly and the
+// centred covariance is S - B B^T / p (FP64 differences and products, as in
+// the path above).
+// ============================================================================
+template <int DT, int NR>
+__global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise, unsigned long long* __restrict__ ctr)
 {
+    extern __shared__ u4v lbuf[];  // the current line, raw storage values
+    const int sidx = blockIdx.x;
+    if (sidx >= P.nstreams) return;  // uniform for the workgroup
+    const StreamDesc d = P.sd ? load_desc(P.sd + sidx) : P.one;
+    const int p = d.p, b = d.b;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    __shared__ double red_s[4][256 + 16];
+    __shared__ double xt_s[16 * 17];
+    __shared__ double nrm_s[4][2];
+    __shared__ float mu_s[16];
+    __shared__ int bad_s;
+
+    typedef typename Raw1<DT>::T RT;
+    const RT* lx = (const RT*)lbuf;
+    const size_t line_elems = (size_t)p * b;
+    const int nq = (int)(line_elems * sizeof(RT) / 16);  // 16-byte words of a line (exact)
+    u4v pf[NR];
+    // unconditional loads of the line's words (clamped to the last one), kept raw
+    auto lload = [&](const void* X, int tl) __attribute__((always_inline)) {
+        const GLB u4v* q = (const GLB u4v*)X;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int i = tl + 256 * r;
+            pf[r] = q[i < nq ? i : nq - 1];
+        }
+    };
+    auto lstore = [&](int tl) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int i = tl + 256 * r;
+            if (i < nq) lbuf[i] = pf[r];
+        }
+    };
+
+    GLB double* state = glb(d.state);
+    double Kst[4] = {0.0, 0.0, 0.0, 0.0}, mst = 0.0;  // wave 0: K (state layout) and mu of band c
+    if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Kst[i] = state[lane * 4 + i];
+        mst = state[256 + c];
+    }
+    const int ntile = (p + 15) >> 4;
+    const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
+
+    if (d.n > 0) lload(d.x, tid);
+    long long t = d.t0;
+    for (int l = 0; l < d.n; ++l, ++t) {
+        // Lane-dependent indices are re-derived each line from a thread index the
+        // compiler cannot see through: hoisted out of the loop, the many masks and
+        // addresses computed from them would stay live across it and spill.
+        int tl = tid;
+        __asm__ volatile("" : "+v"(tl));
+        const int lane = tl & 63, g = lane >> 4, c = lane & 15, band0 = 4 * g;
+        GLB float* out = glb(d.out + (size_t)l * p);
+        __syncthreads();  // the previous line's reads of the buffer are done
+        lstore(tl);
+        if (l + 1 < d.n) lload(advance<DT>(d.x, (size_t)(l + 1) * line_elems), tl);
+        __syncthreads();
+
+        // ---- Gram of tiles w, w+4, ... shifted by pixel 0 (lane (g, c): pixels
+        //      4g..4g+3 of band c), two tiles per step: the next two tiles' LDS
+        //      reads are in flight during this step's products, whose two MFMA
+        //      chains (one accumulator per tile) are interleaved.  Tiles past the
+        //      end read element 0 and are masked to zero.
+        // LDS addresses are clamped into the line (pixel p-1, band b-1) rather than
+        // selected: a select on the address becomes a branch around each read and a
+        // wait after it.  Values outside the line are masked where they are used.
+        const int cb = c < b ? c : b - 1;
+        const double sh = (c < b) ? (double)Raw1<DT>::cvt(lx[cb]) : 0.0;
+        auto graw = [&](int tt, RT (&v)[4]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = 16 * tt + 4 * g + i;
+                v[i] = lx[(px < p ? px : p - 1) * b + cb];
+            }
+        };
+        auto gval = [&](int tt, const RT (&v)[4]) __attribute__((always_inline)) {
+            d4 xv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = 16 * tt + 4 * g + i;
+                xv[i] = (px < p && c < b) ? (double)Raw1<DT>::cvt(v[i]) - sh : 0.0;
+            }
+            return xv;
+        };
+        d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+        double bsd = 0.0;
+        RT ra[4], rb[4];
+        graw(w, ra);
+        graw(w + 4, rb);
+        for (int tt = w; tt < ntile; tt += 8) {
+            const d4 x0 = gval(tt, ra), x1 = gval(tt + 4, rb);
+            graw(tt + 8, ra);
+            graw(tt + 12, rb);
+            bsd += ((x0[0] + x0[1]) + (x0[2] + x0[3])) + ((x1[0] + x1[1]) + (x1[2] + x1[3]));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                acc0 = mfma(x0[k], x0[k], acc0);
+                acc1 = mfma(x1[k], x1[k], acc1);
+            }
+        }
+        bsd += __shfl_xor(bsd, 16);
+        bsd += __shfl_xor(bsd, 32);
+        // FP64 accumulator layout: register i of lane (g, c) is row 4i+g, column c
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red_s[w][(4 * i + g) * 16 + c] = acc0[i] + acc1[i];
+        if (g == 0) red_s[w][256 + c] = bsd;
+        __syncthreads();
+
+        // ---- line statistics, moving averages and factorisation (wave 0)
+        if (w == 0) {
+            const double a = (t == 0) ? 1.0 : d.alpha;
+            const double bc = (red_s[0][256 + c] + red_s[1][256 + c]) + (red_s[2][256 + c] + red_s[3][256 + c]);
+            double aa[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 4 * g + i;
+                const double br =
+                    (red_s[0][256 + row] + red_s[1][256 + row]) + (red_s[2][256 + row] + red_s[3][256 + row]);
+                const double s = (red_s[0][row * 16 + c] + red_s[1][row * 16 + c]) +
+                                 (red_s[2][row * 16 + c] + red_s[3][row * 16 + c]);
+                const double kh = (s - br * bc * inv_p) * inv_p1;
+                Kst[i] = (1.0 - a) * Kst[i] + a * kh;
+                double av = Kst[i];
+                if (row >= b || c >= b) av = (row == c) ? 1.0 : 0.0;
+                else if (row == c) av += d.eps;
+                aa[i] = av;
+            }
+            const double muh = (c < b) ? sh + bc * inv_p : 0.0;
+            mst = (1.0 - a) * mst + a * muh;
+            if (lane < 16) mu_s[lane] = (float)mst;
+            double xx[4];
+            const int bad = factor16(aa, xx, lane, b);
+            // X[4g+i][c], zero in the padded rows and columns: the scores then
+            // need no band mask (padded residual entries are finite, see below)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xt_s[(4 * g + i) * 17 + c] = (4 * g + i < b && c < b) ? xx[i] : 0.0;
+            if (lane == 0) {
+                bad_s = bad;
+                atomicAdd(&ctr[0], 1ull);
+                if (bad) atomicAdd(&ctr[1], 1ull);
+            }
+        }
+        __syncthreads();
+
+        // ---- scores (lane (g, c): bands 4g..4g+3 of pixel c of a tile)
+        const bool bad = bad_s != 0;
+        f4 xt, m4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            xt[i] = (float)xt_s[c * 17 + 4 * g + i];  // X^T[4g+i][c]
+            m4[i] = mu_s[4 * g + i];
+        }
+        double s1 = 0.0, s2 = 0.0;
+        // two tiles per step as in the Gram: next reads in flight, chains interleaved
+        auto sraw = [&](int tt, RT (&v)[4]) __attribute__((always_inline)) {
+            const int px = 16 * tt + c;
+            const int row = (px < p ? px : p - 1) * b;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = lx[row + (band0 + q < b ? band0 + q : b - 1)];
+        };
+        // Reads outside the line were clamped to an element of it, so every
+        // residual entry is finite: padded bands meet zero columns of X and
+        // pixels past p are not stored, so no mask is needed.
+        auto sval = [&](int tt, const RT (&v)[4]) __attribute__((always_inline)) {
+            f4 r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = Raw1<DT>::cvt(v[q]) - m4[q];
+            return r;
+        };
+        auto emit = [&](int tt, const f4 y) __attribute__((always_inline)) {
+            float ss = (y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]);
+            ss += __shfl_xor(ss, 16);
+            ss += __shfl_xor(ss, 32);
+            const float dl = bad ? __builtin_nanf("") : __builtin_amdgcn_sqrtf(ss);
+            const int px = 16 * tt + c;
+            if (g == 0 && px < p) {
+                out[px] = dl;
+                if (normalise) {
+                    s1 += (double)dl;
+                    s2 += (double)dl * (double)dl;
+                }
+            }
+        };
+        RT qa[4], qb[4];
+        sraw(w, qa);
+        sraw(w + 4, qb);
+        for (int tt = w; tt < ntile; tt += 8) {
+            const f4 r0 = sval(tt, qa), r1 = sval(tt + 4, qb);
+            sraw(tt + 8, qa);
+            sraw(tt + 12, qb);
+            f4 y0 = f4{0.f, 0.f, 0.f, 0.f}, y1 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {  // L^{-1} r of pixel c, rows 4g..4g+3
+                y0 = mfma(xt[k], r0[k], y0);
+                y1 = mfma(xt[k], r1[k], y1);
+            }
+            emit(tt, y0);
+            emit(tt + 4, y1);
+        }
+        if (normalise && d.outn) {
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                s1 += __shfl_xor(s1, o);
+                s2 += __shfl_xor(s2, o);
+            }
+            if (lane == 0) {
+                nrm_s[w][0] = s1;
+                nrm_s[w][1] = s2;
+            }
+            __syncthreads();
+            const double m1 = (nrm_s[0][0] + nrm_s[1][0] + nrm_s[2][0] + nrm_s[3][0]) * inv_p;
+            const double m2 = (nrm_s[0][1] + nrm_s[1][1] + nrm_s[2][1] + nrm_s[3][1]) * inv_p;
+            const double var = m2 - m1 * m1;
+            const double sd = var > 0.0 ? sqrt(var) : 0.0;
+            GLB float* outn = glb(d.outn + (size_t)l * p);
+            for (int px = tl; px < p; px += 256)
+                outn[px] = sd > 0.0 ? (float)(((double)out[px] - m1) / sd) : 0.f;
+        }
+    }
+    if (w == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) state[lane * 4 + i] = Kst[i];
+        if (lane < 16) state[256 + lane] = mst;
+    }
+}
+
+// largest line (bytes) the LDS-resident variant takes: 10 words per thread
+constexpr int SMALL_LDS_MAX = 10 * 256 * 16;
+
+template <int DT, int NR>
+static void small_l(const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_small_l<DT, NR>), dim3((unsigned)P.nstreams), dim3(256), (size_t)NR * 256 * 16, s, P,
+                       normalise, ctr);
+}
+
+template <int DT>
+static void small_l(int line_bytes, const Pass& P, int normalise, unsigned long long* ctr, hipStream_t s)
+{
+    if (line_bytes <= 2 * 4096) small_l<DT, 2>(P, normalise, ctr, s);
+    else if (line_bytes <= 4 * 4096) small_l<DT, 4>(P, normalise, ctr, s);
+    else small_l<DT, 10>(P, normalise, ctr, s);
+}
+
+hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, int lds_line_bytes,
+                        hipStream_t s)
+{
+    if (lds_line_bytes > 0 && lds_line_bytes <= SMALL_LDS_MAX) {
+        switch (dtype) {
+        case DT_F32: small_l<DT_F32>(lds_line_bytes, P, normalise, ctr, s); break;
+        case DT_F16: small_l<DT_F16>(lds_line_bytes, P, normalise, ctr, s); break;
+        default: small_l<DT_U16>(lds_line_bytes, P, normalise, ctr, s); break;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)P.nstreams), block(256);
 #define ERX_SMALL(DTV)                                                                                      \
     if (P.vec4) hipLaunchKernelGGL((k_small<DTV, true>), grid, block, 0, s, P, normalise, ctr);            \

@@ -194,6 +194,68 @@ def test_small_band_fused_path_matches_oracle(erx, storage):
     assert bt.stats()["fp64_refactors"] == sum(s[2] for s in specs)
 
 
+def lds_specs(n, seed, esz):
+    """Streams whose every line fits the fused path's LDS buffer (at most 40960 bytes, a
+    multiple of 16 bytes, so each line of a fresh allocation starts 16-byte aligned)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        b = int(rng.integers(1, 17))
+        p = int(rng.choice([2, 8, 16, 96, 304, 640, 1280]))
+        if (p * b * esz) % 16 or p * b * esz > 40960:
+            continue
+        out.append((b, p, int(rng.integers(1, 60)), float(rng.choice([1.0, 0.3, 0.05]))))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "u16"])
+def test_small_band_lds_variant_matches_oracle(erx, storage):
+    """The fused path with each line held in LDS (lines of at most 40960 bytes on 16-byte
+    boundaries), pushed in two uneven parts, against the FP64 oracle and against the
+    variant that streams every tile from device memory."""
+    esz = 4 if storage == "f32" else 2
+    specs = lds_specs(36, {"f32": 11, "f16": 12, "u16": 13}[storage], esz)
+    specs[0] = (16, 40960 // (16 * esz), 9, 0.1)  # the largest line the buffer takes
+    log(f"fused small-band path, line in LDS, {storage}, {len(specs)} streams")
+    data = []
+    for i, (b, p, T, a) in enumerate(specs):
+        sc = datagen.make_scene(53, i, b, p, T, kind="gauss", storage=storage, momentum=a)
+        data.append(datagen.lines(sc, 0, T)[0])
+    dev = [x.cuda() for x in data]
+    cut = [T // 3 for (_, _, T, _) in specs]
+    outs_by_mode = {}
+    for mode in (1, 2):
+        bt = erx.Batch([s[0] for s in specs], [s[1] for s in specs], [s[3] for s in specs], dtype=storage,
+                       small_path=mode)
+        got = [[], []]
+        for part in range(2):
+            chunk = [x[:k] if part == 0 else x[k:] for x, k in zip(dev, cut)]
+            bt.push([c if c.shape[0] else None for c in chunk])
+            got[part] = [None if o is None else o.cpu().numpy() for o in bt.scores()]
+        outs_by_mode[mode] = got
+        if mode == 1:
+            for s, (b, p, T, a) in enumerate(specs):
+                t, mu, K = bt.state(s)
+                o = oracle.run(datagen.storage_to_float64(data[s], storage), a, 1e-5, history=True)
+                assert t == T
+                np.testing.assert_allclose(mu, o["mu_hist"][-1], rtol=1e-5, atol=1e-6)
+                np.testing.assert_allclose(K, o["K_hist"][-1], rtol=1e-4,
+                                           atol=1e-6 * max(1.0, np.abs(o["K_hist"][-1]).max()))
+            assert bt.stats()["fp64_refactors"] == sum(s[2] for s in specs)
+    oras = [oracle.Stream(b, p, a, 1e-5) for (b, p, T, a) in specs]
+    for part in range(2):
+        for s, (b, p, T, a) in enumerate(specs):
+            lo, hi = (0, cut[s]) if part == 0 else (cut[s], T)
+            o1, o2 = outs_by_mode[1][part][s], outs_by_mode[2][part][s]
+            if hi == lo:
+                assert o1 is None and o2 is None
+                continue
+            want = oras[s].push(datagen.storage_to_float64(data[s][lo:hi], storage))["delta"]
+            err = rel_err(o1, want).max()
+            assert err <= TOL, (part, s, b, p, err)
+            assert rel_err(o1, o2.astype(np.float64)).max() <= 2 * TOL, (part, s, b, p)
+
+
 def test_small_band_fused_path_equals_general_path(erx):
     specs = [(b, 640, 50, 0.1) for b in (3, 8, 12, 16)] * 3
     data = []
