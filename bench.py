@@ -172,6 +172,27 @@ def time_workload(erx, torch, X, b, p, momentum, steps, warmup, block_lines, str
     return ms, wall, prof, st
 
 
+def tune_leg(erx, torch, X, b, p, momentum, args, stream, ms_default):
+    """The autotuner on the long-scan shape (one stream) and on the multispectral batch shape
+    (1024 streams of 16 bands, FP16), then the long-scan steps again with the tuned setting."""
+    import tempfile
+    res = {}
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = os.path.join(tmp, "tune.json")
+        t0 = time.perf_counter()
+        r = erx.autotune(b, p, momentum, cache=cache)
+        res["long_scan"] = dict(r, tuning_s=time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        rb = erx.autotune(16, 1280, 0.1, dtype="f16", nstreams=1024, cache=cache)
+        res["multispectral_batch_b16"] = dict(rb, tuning_s=time.perf_counter() - t0)
+    torch.cuda.empty_cache()
+    ms, _, _, _ = time_workload(erx, torch, X, b, p, momentum, args.steps, 1, r["block_lines"], stream,
+                                profile=False, scan_lines=r["scan_lines"])
+    res["long_scan"]["ms_per_step_tuned"] = ms / args.steps
+    res["long_scan"]["ms_per_step_default"] = ms_default
+    return res
+
+
 def batched_leg(erx, torch, cfg, T, stream, mixed):
     """Many independent streams of one workload configuration (each cut to T lines): the batched
     path (shared passes, graph replay) against one handle per stream pushed one after another,
@@ -438,6 +459,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known traffic against "
                          "which the FETCH_SIZE / WRITE_SIZE counters are scaled)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner leg")
     ap.add_argument("--rocprof-summary", nargs="+", metavar="DIR",
                     help="no GPU: print a markdown summary of rocprofv3 CSV output under DIR(s)")
     ap.add_argument("--rocprof-command", default="", help="command line recorded in the summary")
@@ -529,6 +551,10 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = mixed_leg(erx, torch, X, b, p, sc.momentum, args, stream, ms_step, prof)
+
+    if not args.no_tune:
+        print("[bench] autotuning the launch settings", file=sys.stderr, flush=True)
+        out["autotune"] = tune_leg(erx, torch, X, b, p, sc.momentum, args, stream, ms_step)
     del X
     torch.cuda.empty_cache()
 

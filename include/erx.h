@@ -197,6 +197,41 @@ ERX_API int erx_batch_synchronize(erx_batch *bt);
 ERX_API void erx_batch_destroy(erx_batch *bt);
 
 /* ---------------------------------------------------------------------------------------
+ * Autotuning of launch settings (a project addition; the paper has none).  For one
+ * workload shape - a configuration plus the number of identical streams sharing it - the
+ * tuner runs every candidate setting on synthetic lines of that shape (values in
+ * [0.25, 0.75), independent bands) through the entry points above, times each with HIP
+ * events on a stream of its own, and returns the fastest.  Candidates: for one stream,
+ * lines per device pass (block_lines 512..8192) x scan segment (scan_lines 32, 64, 128);
+ * for a batch, pass capacity (1024, 4096, 16384) and, when bands <= 16, the small-band
+ * path mode (erx_batch_small_path 0, 1, 2).  No candidate changes what is computed: pass
+ * and segment lengths only regroup the FP64 moving-average updates (scores agree with an
+ * untuned handle's to 1e-6 relative), and the small-band modes agree with the general
+ * path as erx_batch_small_path states.  The timings are those of well-conditioned
+ * backgrounds (no FP64 re-factor triggered).
+ * ------------------------------------------------------------------------------------- */
+typedef struct erx_tune_result {
+    int block_lines;    /* erx_config.block_lines to use */
+    int scan_lines;     /* erx_config.scan_lines to use */
+    int small_path;     /* erx_batch_small_path mode to use; -1 for a single stream */
+    int candidates;     /* settings timed by this call; 0 when the result came from the cache */
+    double us_per_line; /* measured microseconds per line (per stream line for a batch) */
+} erx_tune_result;
+/* cfg: the workload (its block_lines and scan_lines are ignored); nstreams >= 1 (1: a
+ * detector made with erx_create_ex, more: a batch of that many streams of cfg's shape);
+ * cache_path: a JSON file {"erx_tune": 1, "entries": [...]} that is read first (an entry
+ * for the same bands, pixels, dtype, precision, fp64_cond_threshold, normalise and
+ * nstreams is returned without timing) and updated with a new result, or NULL.  Uses the
+ * current HIP device and allocates the synthetic input (at most 4 GiB) for the duration
+ * of the call.  ERX_EINVAL for invalid arguments or an unreadable cache file (nothing is
+ * timed), ERX_ENOMEM / ERX_EDEVICE on device failures. */
+ERX_API int erx_autotune(const erx_config *cfg, int nstreams, const char *cache_path, erx_tune_result *out);
+/* Cache lookup only (no device work): ERX_OK with *out filled when cache_path holds an
+ * entry for (cfg, nstreams), ERX_ESTATE when it holds none (or the file does not exist),
+ * ERX_EINVAL for invalid arguments or a file that is not a tuning cache. */
+ERX_API int erx_tune_lookup(const erx_config *cfg, int nstreams, const char *cache_path, erx_tune_result *out);
+
+/* ---------------------------------------------------------------------------------------
  * Learned band-projection surrogate (a stated change to the method, the learned analogue of
  * the sparse random projection of Sec. III-B).  For b-band FP32 lines:
  *     z = W x + c (ERX_SURR_K outputs),  u = L_z^{-1} (z - mu_z) with (mu_z, L_z) the ERX

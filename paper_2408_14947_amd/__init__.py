@@ -34,7 +34,7 @@ EXPORTS = (
     "erx_surrogate_get_params", "erx_surrogate_scores", "erx_surrogate_train_step",
     "erx_surrogate_grads", "erx_surrogate_destroy", "erx_surrogate_detector_create",
     "erx_surrogate_detector_push", "erx_surrogate_detector_scores", "erx_surrogate_detector_status",
-    "erx_surrogate_detector_destroy",
+    "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup",
 )
 SURR_K, SURR_HIDDEN = 16, 64
 
@@ -51,6 +51,11 @@ class Config(C.Structure):
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
                 ("cond_estimate", C.c_int)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("block_lines", C.c_int), ("scan_lines", C.c_int), ("small_path", C.c_int),
+                ("candidates", C.c_int), ("us_per_line", C.c_double)]
 
 
 class KernelTime(C.Structure):
@@ -118,6 +123,8 @@ def load(path: str = LIB_PATH):
         "erx_surrogate_detector_status": (ip, [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong),
                                                 C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
         "erx_surrogate_detector_destroy": (None, [vp]),
+        "erx_autotune": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
+        "erx_tune_lookup": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -404,6 +411,44 @@ __all__ = ["Detector", "Batch", "ErxError", "load", "last_error", "EXPORTS", "DT
 # learned projection surrogate
 # ---------------------------------------------------------------------------
 PARAM_ORDER = ("W", "c", "A1", "a1", "w2", "c2")
+
+
+def _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise):
+    cfg = Config()
+    load().erx_config_default(C.byref(cfg), int(bands), int(pixels), float(momentum))
+    cfg.dtype = DTYPES[dtype]
+    cfg.precision = PRECISIONS[precision]
+    cfg.fp64_cond_threshold = float(fp64_cond_threshold)
+    cfg.normalise = 1 if normalise else 0
+    return cfg
+
+
+def _tune_dict(r):
+    return {"block_lines": r.block_lines, "scan_lines": r.scan_lines, "small_path": r.small_path,
+            "candidates": r.candidates, "us_per_line": r.us_per_line}
+
+
+def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32", precision: str = "fp32",
+             fp64_cond_threshold: float = 0.0, normalise: bool = False, nstreams: int = 1,
+             cache: Optional[str] = None) -> dict:
+    """Fastest launch setting for a workload shape (erx_autotune): block_lines, scan_lines,
+    small_path (batch mode, -1 for one stream), candidates timed, us_per_line."""
+    lib = load()
+    cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise)
+    r = TuneResult()
+    _check(lib.erx_autotune(C.byref(cfg), int(nstreams), cache.encode() if cache else None, C.byref(r)))
+    return _tune_dict(r)
+
+
+def tune_lookup(bands: int, pixels: int, cache: str, momentum: float = 0.1, dtype: str = "f32",
+                precision: str = "fp32", fp64_cond_threshold: float = 0.0, normalise: bool = False,
+                nstreams: int = 1) -> Optional[dict]:
+    """Cached setting for a workload shape (erx_tune_lookup), or None when the cache has none."""
+    lib = load()
+    cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise)
+    r = TuneResult()
+    rc = _check(lib.erx_tune_lookup(C.byref(cfg), int(nstreams), cache.encode(), C.byref(r)), allow=(ERX_ESTATE,))
+    return None if rc == ERX_ESTATE else _tune_dict(r)
 
 
 def _param_shapes(bands):

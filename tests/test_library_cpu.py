@@ -69,3 +69,34 @@ def test_defaults():
     assert (cfg.bands, cfg.pixels, cfg.dtype, cfg.precision) == (108, 640, 0, 0)
     assert abs(cfg.ridge - 1e-5) < 1e-12 and cfg.fp64_cond_threshold == 0.0
     assert cfg.block_lines == 2048 and cfg.scan_lines == 64
+
+
+def test_tune_cache_lookup(tmp_path):
+    """The autotuner's JSON cache is read without any device work: an entry for the
+    same shape is returned, another shape gives None, a file of another form is an
+    error (and a missing file an empty cache)."""
+    erx, _ = _lib()
+    path = str(tmp_path / "tune.json")
+    assert erx.tune_lookup(224, 1024, path) is None  # no file yet
+    with open(path, "w") as f:
+        f.write('{"erx_tune": 1, "entries": [\n'
+                '  {"bands": 224, "pixels": 1024, "dtype": 0, "precision": 0, "normalise": 0, "nstreams": 1, '
+                '"fp64_cond_threshold": 0, "block_lines": 4096, "scan_lines": 32, "small_path": -1, '
+                '"us_per_line": 11.5},\n'
+                '  {"bands": 8, "pixels": 1280, "dtype": 1, "precision": 0, "normalise": 0, "nstreams": 1024, '
+                '"fp64_cond_threshold": 0, "block_lines": 1024, "scan_lines": 64, "small_path": 1, '
+                '"us_per_line": 0.04}\n]}\n')
+    r = erx.tune_lookup(224, 1024, path)
+    assert r == {"block_lines": 4096, "scan_lines": 32, "small_path": -1, "candidates": 0, "us_per_line": 11.5}
+    r = erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1024)
+    assert r["small_path"] == 1 and r["block_lines"] == 1024
+    assert erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1) is None        # other stream count
+    assert erx.tune_lookup(224, 1024, path, precision="bf16") is None             # other precision
+    assert erx.tune_lookup(224, 1024, path, fp64_cond_threshold=1e6) is None      # other threshold
+    with open(path, "w") as f:
+        f.write('{"something": "else"}\n')
+    with pytest.raises(erx.ErxError) as e:
+        erx.tune_lookup(224, 1024, path)
+    assert e.value.code == erx.ERX_EINVAL
+    with pytest.raises(erx.ErxError):
+        erx.autotune(224, 1024, nstreams=0)  # rejected before any device work
