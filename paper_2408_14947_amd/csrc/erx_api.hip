@@ -384,7 +384,11 @@ int erx_set_state(erx_ctx* h, long long t, const double* mu, const double* K)
     if (t > 0) {
         for (int j = 0; j < b; ++j) s[(size_t)h->NTL * 256 + j] = mu[j];
         for (int r = 0; r < b; ++r)
-            for (int c = r; c < b; ++c) s[packed_offset(r, c, NT)] = K[(size_t)r * b + c];
+            for (int c = r; c < b; ++c) {
+                s[packed_offset(r, c, NT)] = K[(size_t)r * b + c];
+                // diagonal tiles are stored whole (both triangles), as the kernels write them
+                if ((r >> 4) == (c >> 4)) s[packed_offset(c, r, NT)] = K[(size_t)c * b + r];
+            }
     }
     HIPCHK(hipMemcpyAsync(h->state, s.data(), h->E * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
