@@ -215,21 +215,24 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         rok[j] = rband + j < b;
         cok[j] = cband + j < b;
     }
-    f4 pr[4], pc[4];
+    // two register sets of fetched chunks: chunk j is staged from set j & 1
+    f4 pr2[2][4], pc2[2][4];
+    f4(&pr)[4] = pr2[0];
+    f4(&pc)[4] = pc2[0];
     // unconditional: past the last pixel the addresses are clamped into the
     // line and the values are masked by stage()
-    auto fetch = [&](int k0) __attribute__((always_inline)) {
+    auto fetch = [&](int k0, f4(&fr)[4], f4(&fc)[4]) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int px = k0 + 4 * pq + r;
             const bool okp = px < p;
             const size_t row = (size_t)(okp ? px : 0) * b;
             const bool okr = okp && rok[0], okc = okp && cok[0];
-            pr[r] = ldq<DT, VEC>(X, okr ? row + rband : 0, okr ? b - rband : 0);
-            if (!dg) pc[r] = ldq<DT, VEC>(X, okc ? row + cband : 0, okc ? b - cband : 0);
+            fr[r] = ldq<DT, VEC>(X, okr ? row + rband : 0, okr ? b - rband : 0);
+            if (!dg) fc[r] = ldq<DT, VEC>(X, okc ? row + cband : 0, okc ? b - cband : 0);
         }
     };
-    fetch(0);
+    fetch(0, pr2[0], pc2[0]);
     {
         // shift from the first chunk: per-thread sums of 4 pixels, then the 4
         // pixel quads of a wave (lanes bg + 16k), then the 4 waves via LDS
@@ -275,7 +278,7 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         sr[j] = sc[j] = 0.f;
         dsr[j] = dsc[j] = 0.0;
     }
-    auto stage = [&](int k0, int buf) __attribute__((always_inline)) {
+    auto stage = [&](int k0, int buf, const f4(&fr)[4], const f4(&fc)[4]) __attribute__((always_inline)) {
         uint32_t* Rb = Rt + buf * G::WORDS;
         uint32_t* Cb = Ct + buf * G::WORDS;
         const int nv = p - k0 - 4 * pq;  // valid pixels among this thread's four
@@ -283,12 +286,12 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         for (int j = 0; j < 4; ++j) {
             f4 v;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = (r < nv && rok[j]) ? pr[r][j] - shr[j] : 0.f;
+            for (int r = 0; r < 4; ++r) v[r] = (r < nv && rok[j]) ? fr[r][j] - shr[j] : 0.f;
             sr[j] += (v[0] + v[1]) + (v[2] + v[3]);
             G::put(Rb, 4 * bg + j, pq, v);
             if (!dg) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = (r < nv && cok[j]) ? pc[r][j] - shc[j] : 0.f;
+                for (int r = 0; r < 4; ++r) v[r] = (r < nv && cok[j]) ? fc[r][j] - shc[j] : 0.f;
                 sc[j] += (v[0] + v[1]) + (v[2] + v[3]);
                 G::put(Cb, 4 * bg + j, pq, v);
             }
@@ -310,15 +313,15 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // Double-buffered LDS: the products of chunk j read buffer j & 1 while the
-    // staging of chunk j+1 (from registers) fills the other buffer and the
-    // loads of chunk j+2 are issued; one barrier per chunk.  Staging and
-    // fetching run unconditionally (past the last pixel they stage zeros and
-    // load clamped addresses), so no load sits under a branch.
-    stage(0, 0);
-    fetch(64);
-    __syncthreads();
-    for (int k0 = 0, it = 0; k0 < p; k0 += 64, ++it) {
+    // Double-buffered LDS, two register sets: the products of chunk j read LDS
+    // buffer j & 1 while chunk j+1 is staged (from register set (j+1) & 1)
+    // into the other buffer and the loads of chunk j+3 are issued into the set
+    // just staged, so a chunk's loads have two chunks of products to land; one
+    // barrier per chunk.  Staging and fetching run unconditionally (past the
+    // last pixel they stage zeros and load clamped addresses), so no load sits
+    // under a branch.  The loop is unrolled by two so that the register sets
+    // are named statically.
+    auto step = [&](int k0, int it, f4(&sr_)[4], f4(&sc_)[4]) __attribute__((always_inline)) {
         const uint32_t* Rb = Rt + (it & 1) * G::WORDS;
         const uint32_t* Cb = dg ? Rb : (const uint32_t*)(Ct + (it & 1) * G::WORDS);
         if (rowok) {
@@ -344,9 +347,18 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
                 sr[j] = sc[j] = 0.f;
             }
         }
-        stage(k0 + 64, (it + 1) & 1);
-        fetch(k0 + 128);
+        stage(k0 + 64, (it + 1) & 1, sr_, sc_);  // chunk j+1 from its set ...
+        fetch(k0 + 192, sr_, sc_);               // ... which then receives chunk j+3
         __syncthreads();
+    };
+    stage(0, 0, pr2[0], pc2[0]);
+    fetch(64, pr2[1], pc2[1]);
+    fetch(128, pr2[0], pc2[0]);
+    __syncthreads();
+    for (int k0 = 0, it = 0; k0 < p; k0 += 128, it += 2) {
+        step(k0, it, pr2[1], pc2[1]);
+        if (k0 + 64 >= p) break;
+        step(k0 + 64, it + 1, pr2[0], pc2[0]);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
