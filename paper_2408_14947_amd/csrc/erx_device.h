@@ -6,6 +6,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 #include <type_traits>
+#include <utility>
 
 #include "erx_internal.h"
 
@@ -211,6 +212,107 @@ __device__ __forceinline__ int factor_diag16(T* diag_s, T* xt_s, int lane)
     if (lane < 16)
 #pragma unroll
         for (int q = 0; q < 16; ++q) xt_s[q * 17 + lane] = x[q];  // xt[row][col] = X[row][col]
+    return bad;
+}
+
+// Cholesky factor L of a 16x16 FP64 block A and its inverse X = L^{-1}, by one
+// wave holding both in the state layout (lane (g, c), register i: row 4g+i,
+// column c): four values per lane, so the factorisation costs the kernel few
+// registers.  Right-looking: at step k the pivot comes from lane (k/4, k), the
+// rows of column k from lane (g, k) of each lane's own row group (a DPP row
+// broadcast), and entry
+// (c, k) from lane (k/4, c) through the symmetry of the trailing block (both
+// triangles are updated).  Row k of X is eliminated in the same step: it needs
+// only column k of L and the rows of X above it, which are final by then.
+// On entry a holds A (both triangles); on return a holds L (zero above the
+// diagonal) and x holds X.  When rows and columns nb..15 of A are those of the
+// identity (padded bands) the steps from nb on change nothing and are skipped.
+// Returns 1 if a pivot was not positive (a NaN pivot propagates and is not
+// counted).
+// value of lane K of each row of 16 lanes (DPP row_newbcast), for an FP64 value
+template <int K> __device__ __forceinline__ double row_bcast(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), 0x150 + K, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), 0x150 + K, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int K>
+__device__ __forceinline__ void factor16_step(double (&a)[4], double (&x)[4], int g, int c, int& bad)
+{
+    constexpr int kg = K >> 2, ki = K & 3;
+    double ar[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ar[i] = row_bcast<K>(a[i]);  // A[4g+i][K]: lane K of the lane's row
+    const double ac = __shfl(a[ki], 16 * kg + c);           // A[K][c] = A[c][K]
+    const double akk = bcast(a[ki], 16 * kg + K);
+    if (!(akk > 0.0) && !(akk != akk)) bad = 1;
+    const double inv = rsqrt_nr(akk);
+    double lr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * g + i;
+        lr[i] = r > K ? ar[i] * inv : (r == K ? akk * inv : 0.0);  // L[r][K]
+    }
+    const double lc = c > K ? ac * inv : 0.0;                      // L[c][K] below the pivot
+    if (g == kg) x[ki] *= inv;                                     // row K of X is final
+    const double xk = __shfl(x[ki], 16 * kg + c);                  // X[K][c]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * g + i;
+        if (c == K) a[i] = lr[i];
+        else if (r > K && c > K) a[i] -= lr[i] * lc;
+        if (r > K) x[i] -= lr[i] * xk;
+    }
+}
+
+template <int... Ks>
+__device__ __forceinline__ void factor16_steps(std::integer_sequence<int, Ks...>, double (&a)[4], double (&x)[4],
+                                               int g, int c, int nb, int& bad)
+{
+    // rows and columns from nb on are the identity and stay so
+    ((Ks < nb ? factor16_step<Ks>(a, x, g, c, bad) : void()), ...);
+}
+
+__device__ __forceinline__ int factor16(double (&a)[4], double (&x)[4], int lane, int nb = 16)
+{
+    const int g = lane >> 4, c = lane & 15;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = (4 * g + i == c) ? 1.0 : 0.0;
+    factor16_steps(std::make_integer_sequence<int, 16>(), a, x, g, c, nb, bad);
+    return bad;
+}
+
+
+// The FP64 instantiation with the contract of factor_diag16 above (the block's
+// lower triangle in diag_s, L back in diag_s with zeros above the diagonal,
+// X = L^{-1} in xt_s), computed by the register-lean factor16 on the block
+// mirrored from its lower triangle.  The lane index is re-derived from a value
+// the compiler cannot see through, so that the lane masks of the sixteen
+// steps are not hoisted out of a caller's loop (where they would stay live).
+template <>
+__device__ __forceinline__ int factor_diag16<double>(double* diag_s, double* xt_s, int lane)
+{
+    int ln = lane;
+    __asm__ volatile("" : "+v"(ln));
+    const int g = ln >> 4, c = ln & 15;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double a[4], x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * g + i;
+        a[i] = r >= c ? diag_s[r * 17 + c] : diag_s[c * 17 + r];
+    }
+    const int bad = factor16(a, x, ln);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        diag_s[(4 * g + i) * 17 + c] = a[i];
+        xt_s[(4 * g + i) * 17 + c] = x[i];
+    }
     return bad;
 }
 

@@ -1156,7 +1156,7 @@ hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double*
 
 template <class T, int NT> constexpr int chol_waves()
 {
-    return NT <= 6 ? 4 : 8;
+    return NT <= 6 ? 4 : (NT <= 10 ? 8 : 16);
 }
 
 template <class T, int NT>
