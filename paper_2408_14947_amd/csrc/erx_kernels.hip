@@ -138,7 +138,7 @@ template <> struct G4<ERX_GRAM_FP32> {
     }
     template <int NQ>
     static __device__ __forceinline__ void chunk(const uint32_t* Rt, const uint32_t* Cp, int w, int c, int g,
-                                                 int kend, f4* acc)
+                                                 int kend, int qoff, f4* acc)
     {
         const int ra = 16 * w + c;
         for (int u = 0; u < kend; u += 16) {
@@ -147,7 +147,7 @@ template <> struct G4<ERX_GRAM_FP32> {
             f4 bv[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int rb = 16 * q + c;
+                const int rb = 16 * (q + qoff) + c;
                 bv[q] = *(const f4*)&Cp[rb * 64 + 4 * (qd ^ g4_sw(rb))];
             }
 #pragma unroll
@@ -169,7 +169,7 @@ template <int PREC> struct G4H {
     }
     template <int NQ>
     static __device__ __forceinline__ void chunk(const uint32_t* Rt, const uint32_t* Cp, int w, int c, int g,
-                                                 int kend, f4* acc)
+                                                 int kend, int qoff, f4* acc)
     {
         const uint16_t* RH = (const uint16_t*)Rt;
         const uint16_t* CH = (const uint16_t*)Cp;
@@ -179,7 +179,7 @@ template <int PREC> struct G4H {
             const v8 av = *(const v8*)&RH[ra * 64 + 8 * (oc ^ g4_sw8(ra))];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int rb = 16 * q + c;
+                const int rb = 16 * (q + qoff) + c;
                 const v8 bv = *(const v8*)&CH[rb * 64 + 8 * (oc ^ g4_sw8(rb))];
                 acc[q] = LP<PREC>::mma(av, bv, acc[q]);
             }
@@ -298,10 +298,15 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         }
     };
 
-    const int nq = __builtin_amdgcn_readfirstlane((NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4);
+    // Column tiles of this wave: 4MJ + qoff + q for q < nq.  In a diagonal
+    // macro tile wave w needs only the tiles on and right of the diagonal
+    // (qoff = w): the tiles below it are neither computed nor stored.
+    const int qoff = dg ? w : 0;
+    const int ncol = (NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4;
+    const int nq = __builtin_amdgcn_readfirstlane(ncol - qoff > 0 ? ncol - qoff : 1);
     int tbits = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) tbits |= (rowok && (4 * MJ + q) < NT && (!dg || q >= w)) ? (1 << q) : 0;
+    for (int q = 0; q < 4; ++q) tbits |= (rowok && q < nq) ? (1 << q) : 0;
     tbits = __builtin_amdgcn_readfirstlane(tbits);
 
     double S[4][4];
@@ -327,10 +332,10 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         if (rowok) {
             const int kend = (p - k0) < 64 ? (p - k0) : 64;
             switch (nq) {
-            case 1: G::template chunk<1>(Rb, Cb, w, c, g, kend, acc); break;
-            case 2: G::template chunk<2>(Rb, Cb, w, c, g, kend, acc); break;
-            case 3: G::template chunk<3>(Rb, Cb, w, c, g, kend, acc); break;
-            default: G::template chunk<4>(Rb, Cb, w, c, g, kend, acc); break;
+            case 1: G::template chunk<1>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+            case 2: G::template chunk<2>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+            case 3: G::template chunk<3>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+            default: G::template chunk<4>(Rb, Cb, w, c, g, kend, qoff, acc); break;
             }
         }
         if (((k0 + 64) % G::FLUSH) == 0 || k0 + 64 >= p) {
@@ -393,14 +398,14 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (!(tbits & (1 << q))) continue;
-        const double scol = bsum_s[64 + 16 * q + c];
+        const double scol = bsum_s[64 + 16 * (q + qoff) + c];
         double o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const double srho = bsum_s[16 * w + 4 * g + i];
             o[i] = (S[q][i] - srho * scol * inv_p) * inv_p1;
         }
-        double* dst = ls + tile_u(I, 4 * MJ + q, NT) * 256 + lane * 4;
+        double* dst = ls + tile_u(I, 4 * MJ + qoff + q, NT) * 256 + lane * 4;
         *(double2*)dst = double2{o[0], o[1]};
         *(double2*)(dst + 2) = double2{o[2], o[3]};
     }
