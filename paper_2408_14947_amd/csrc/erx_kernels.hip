@@ -141,19 +141,41 @@ template <> struct G4<ERX_GRAM_FP32> {
                                                  int kend, int qoff, f4* acc)
     {
         const int ra = 16 * w + c;
-        for (int u = 0; u < kend; u += 16) {
+        // operands of 16 pixels (four per lane)
+        auto rd = [&](int u, f4& av, f4 (&bv)[NQ]) __attribute__((always_inline)) {
             const int qd = (u >> 2) + g;
-            const f4 av = *(const f4*)&Rt[ra * 64 + 4 * (qd ^ g4_sw(ra))];
-            f4 bv[NQ];
+            av = *(const f4*)&Rt[ra * 64 + 4 * (qd ^ g4_sw(ra))];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int rb = 16 * (q + qoff) + c;
                 bv[q] = *(const f4*)&Cp[rb * 64 + 4 * (qd ^ g4_sw(rb))];
             }
+        };
+        auto mul = [&](const f4& av, const f4 (&bv)[NQ]) __attribute__((always_inline)) {
 #pragma unroll
             for (int st = 0; st < 4; ++st)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) acc[q] = mfma(av[st], bv[q][st], acc[q]);
+        };
+        if (kend == 64) {
+            // full chunk: the reads of step k+1 are issued before the products of
+            // step k (scheduling barriers keep the compiler from sinking them
+            // back next to their use), so LDS latency overlaps the MFMAs
+            f4 av[4], bv[4][NQ];
+            rd(0, av[0], bv[0]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < 3) rd(16 * (k + 1), av[k + 1], bv[k + 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                mul(av[k], bv[k]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            for (int u = 0; u < kend; u += 16) {
+                f4 av, bv[NQ];
+                rd(u, av, bv);
+                mul(av, bv);
+            }
         }
     }
 };
