@@ -992,24 +992,20 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
     const float* mu = mu32 + (size_t)line * 16 * NT;
     const f4* Ml = (const f4*)(Mt + (size_t)line * NTL * 256);
 
-    __shared__ f4 Ms[2][NT * 64];
+    // staging buffers padded to whole rounds of 256 threads, so that the
+    // stores need no condition (a conditional store, or a select on a load
+    // address, becomes a branch with a wait for every load in flight)
+    __shared__ f4 Ms[2][MR * 256];
     f4 st[MR];
     auto gload = [&](int K) __attribute__((always_inline)) {
         const int n = (NT - K) * 64;
         const f4* src = Ml + (size_t)tile_lc(K, K, NT) * 64;
 #pragma unroll
-        for (int i = 0; i < MR; ++i) {
-            const int q = tid + 256 * i;
-            st[i] = src[q < n ? q : 0];
-        }
+        for (int i = 0; i < MR; ++i) st[i] = src[min(tid + 256 * i, n - 1)];
     };
     auto lstore = [&](int K, int buf) __attribute__((always_inline)) {
-        const int n = (NT - K) * 64;
 #pragma unroll
-        for (int i = 0; i < MR; ++i) {
-            const int q = tid + 256 * i;
-            if (q < n) Ms[buf][q] = st[i];
-        }
+        for (int i = 0; i < MR; ++i) Ms[buf][tid + 256 * i] = st[i];
     };
     f4 y[2][PT];
     auto yload = [&](int K, f4* yy) __attribute__((always_inline)) {
@@ -1028,8 +1024,13 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
 #pragma unroll
         for (int t = 0; t < PT; ++t) acc[J][t] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // mu of a column's bands, loaded with the column's pixels (a load consumed
+    // right away would make the wait cover every prefetch in flight)
+    f4 mv[2];
+    auto mload = [&](int K, f4& m) __attribute__((always_inline)) { m = *(const GLB f4*)glb(mu + 16 * K + 4 * g); };
     gload(0);
     yload(0, y[0]);
+    mload(0, mv[0]);
     lstore(0, 0);
     __syncthreads();
 #pragma unroll
@@ -1037,11 +1038,15 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
         if (K + 1 < NT) {
             gload(K + 1);
             yload(K + 1, y[(K + 1) & 1]);
+            mload(K + 1, mv[(K + 1) & 1]);
         }
+        // keep the next column's loads here, ahead of this column's products
+        // (left to itself the compiler sinks them next to their use)
+        __builtin_amdgcn_sched_barrier(0);
         // residual of this column's bands: missing pixels and bands are zero
         // (padded bands also have mu 0)
         const int band0 = 16 * K + 4 * g;
-        const f4 m4 = *(const f4*)(mu + band0);
+        const f4 m4 = mv[K & 1];
         f4 r[PT];
 #pragma unroll
         for (int t = 0; t < PT; ++t) {
@@ -1056,6 +1061,7 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
 #pragma unroll
             for (int t = 0; t < PT; ++t) acc[J][t] = mma_xty(acc[J][t], xm, r[t]);
         }
+        __builtin_amdgcn_sched_barrier(0);
         if (K + 1 < NT) lstore(K + 1, (K + 1) & 1);
         __syncthreads();
     }
