@@ -1055,11 +1055,17 @@ __global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __r
             for (int q = 0; q < 4; ++q) r[t][q] = (okp && band0 + q < b) ? y[K & 1][t][q] - m4[q] : 0.f;
         }
         const f4* Mc = Ms[K & 1];
+        // the tile of row J+1 is read before the products of row J
+        f4 xm = Mc[lane];
 #pragma unroll
         for (int J = K; J < NT; ++J) {
-            const f4 xm = Mc[(J - K) * 64 + lane];
+            f4 xn;
+            if (J + 1 < NT) xn = Mc[(J + 1 - K) * 64 + lane];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < PT; ++t) acc[J][t] = mma_xty(acc[J][t], xm, r[t]);
+            __builtin_amdgcn_sched_barrier(0);
+            xm = xn;
         }
         __builtin_amdgcn_sched_barrier(0);
         if (K + 1 < NT) lstore(K + 1, (K + 1) & 1);
