@@ -256,14 +256,17 @@ __device__ __forceinline__ void factor16_step(double (&a)[4], double (&x)[4], in
         lr[i] = r > K ? ar[i] * inv : (r == K ? akk * inv : 0.0);  // L[r][K]
     }
     const double lc = c > K ? ac * inv : 0.0;                      // L[c][K] below the pivot
-    if (g == kg) x[ki] *= inv;                                     // row K of X is final
+    x[ki] = (g == kg) ? x[ki] * inv : x[ki];                       // row K of X is final
     const double xk = __shfl(x[ki], 16 * kg + c);                  // X[K][c]
+    // Branch-free updates.  lr is zero above row K and lc zero up to column K,
+    // so the rank-one update changes only the trailing block and row K of the
+    // columns right of K; those entries are above the diagonal and are
+    // overwritten with the column of L at their own step.
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = 4 * g + i;
-        if (c == K) a[i] = lr[i];
-        else if (r > K && c > K) a[i] -= lr[i] * lc;
-        if (r > K) x[i] -= lr[i] * xk;
+        a[i] = (c == K) ? lr[i] : a[i] - lr[i] * lc;
+        x[i] -= (r > K ? lr[i] : 0.0) * xk;
     }
 }
 
