@@ -196,14 +196,34 @@ template <int PREC> struct G4H {
         const uint16_t* RH = (const uint16_t*)Rt;
         const uint16_t* CH = (const uint16_t*)Cp;
         const int ra = 16 * w + c;
-        for (int u = 0; u < kend; u += 32) {
+        // operands of 32 pixels (eight per lane)
+        auto rd = [&](int u, v8& av, v8 (&bv)[NQ]) __attribute__((always_inline)) {
             const int oc = (u >> 3) + g;
-            const v8 av = *(const v8*)&RH[ra * 64 + 8 * (oc ^ g4_sw8(ra))];
+            av = *(const v8*)&RH[ra * 64 + 8 * (oc ^ g4_sw8(ra))];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const int rb = 16 * (q + qoff) + c;
-                const v8 bv = *(const v8*)&CH[rb * 64 + 8 * (oc ^ g4_sw8(rb))];
-                acc[q] = LP<PREC>::mma(av, bv, acc[q]);
+                bv[q] = *(const v8*)&CH[rb * 64 + 8 * (oc ^ g4_sw8(rb))];
+            }
+        };
+        auto mul = [&](const v8& av, const v8 (&bv)[NQ]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] = LP<PREC>::mma(av, bv[q], acc[q]);
+        };
+        if (kend == 64) {
+            // both 32-pixel steps' reads first, so the second overlaps the
+            // first step's products (as in the FP32 chunk)
+            v8 av[2], bv[2][NQ];
+            rd(0, av[0], bv[0]);
+            rd(32, av[1], bv[1]);
+            __builtin_amdgcn_sched_barrier(0);
+            mul(av[0], bv[0]);
+            mul(av[1], bv[1]);
+        } else {
+            for (int u = 0; u < kend; u += 32) {
+                v8 av, bv[NQ];
+                rd(u, av, bv);
+                mul(av, bv);
             }
         }
     }
