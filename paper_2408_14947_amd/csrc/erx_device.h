@@ -238,7 +238,9 @@ template <int K> __device__ __forceinline__ double row_bcast(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int K>
+// BF: branch-free row updates (fewer instructions; more registers live, which
+// spills in callers that already hold many tiles in registers)
+template <int K, bool BF>
 __device__ __forceinline__ void factor16_step(double (&a)[4], double (&x)[4], int g, int c, int& bad)
 {
     constexpr int kg = K >> 2, ki = K & 3;
@@ -256,35 +258,48 @@ __device__ __forceinline__ void factor16_step(double (&a)[4], double (&x)[4], in
         lr[i] = r > K ? ar[i] * inv : (r == K ? akk * inv : 0.0);  // L[r][K]
     }
     const double lc = c > K ? ac * inv : 0.0;                      // L[c][K] below the pivot
-    x[ki] = (g == kg) ? x[ki] * inv : x[ki];                       // row K of X is final
-    const double xk = __shfl(x[ki], 16 * kg + c);                  // X[K][c]
-    // Branch-free updates.  lr is zero above row K and lc zero up to column K,
-    // so the rank-one update changes only the trailing block and row K of the
-    // columns right of K; those entries are above the diagonal and are
-    // overwritten with the column of L at their own step.
+    if (BF) {
+        x[ki] = (g == kg) ? x[ki] * inv : x[ki];                   // row K of X is final
+        const double xk = __shfl(x[ki], 16 * kg + c);              // X[K][c]
+        // lr is zero above row K and lc zero up to column K, so the rank-one
+        // update changes only the trailing block and row K of the columns right
+        // of K; those entries are above the diagonal and are overwritten with
+        // the column of L at their own step.
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = 4 * g + i;
-        a[i] = (c == K) ? lr[i] : a[i] - lr[i] * lc;
-        x[i] -= (r > K ? lr[i] : 0.0) * xk;
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * g + i;
+            a[i] = (c == K) ? lr[i] : a[i] - lr[i] * lc;
+            x[i] -= (r > K ? lr[i] : 0.0) * xk;
+        }
+    } else {
+        if (g == kg) x[ki] *= inv;
+        const double xk = __shfl(x[ki], 16 * kg + c);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * g + i;
+            if (c == K) a[i] = lr[i];
+            else if (r > K && c > K) a[i] -= lr[i] * lc;
+            if (r > K) x[i] -= lr[i] * xk;
+        }
     }
 }
 
-template <int... Ks>
+template <bool BF, int... Ks>
 __device__ __forceinline__ void factor16_steps(std::integer_sequence<int, Ks...>, double (&a)[4], double (&x)[4],
                                                int g, int c, int nb, int& bad)
 {
     // rows and columns from nb on are the identity and stay so
-    ((Ks < nb ? factor16_step<Ks>(a, x, g, c, bad) : void()), ...);
+    ((Ks < nb ? factor16_step<Ks, BF>(a, x, g, c, bad) : void()), ...);
 }
 
+template <bool BF = true>
 __device__ __forceinline__ int factor16(double (&a)[4], double (&x)[4], int lane, int nb = 16)
 {
     const int g = lane >> 4, c = lane & 15;
     int bad = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) x[i] = (4 * g + i == c) ? 1.0 : 0.0;
-    factor16_steps(std::make_integer_sequence<int, 16>(), a, x, g, c, nb, bad);
+    factor16_steps<BF>(std::make_integer_sequence<int, 16>(), a, x, g, c, nb, bad);
     return bad;
 }
 
@@ -310,7 +325,7 @@ __device__ __forceinline__ int factor_diag16<double>(double* diag_s, double* xt_
         const int r = 4 * g + i;
         a[i] = r >= c ? diag_s[r * 17 + c] : diag_s[c * 17 + r];
     }
-    const int bad = factor16(a, x, ln);
+    const int bad = factor16<false>(a, x, ln);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         diag_s[(4 * g + i) * 17 + c] = a[i];
