@@ -269,9 +269,11 @@ ERX_API void erx_surrogate_destroy(erx_surr *net);
 /* A stream scored by the surrogate and checked against plain ERX: line t with (t+1) %
  * check_every == 0 is also scored by plain ERX and by the surrogate, each on a state that
  * sees only those lines (momentum 1 - (1 - momentum)^check_every); the drift of a check is
- * the median over the line's pixels of |log surrogate - log plain| of those two scores.  After two consecutive checks with drift
- * above drift_threshold the stream switches to plain ERX (re-initialised from the next line)
- * for good.  The detector keeps a pointer to net, which must outlive it. */
+ * the median over the line's pixels of |log surrogate - log plain| of those two scores.
+ * After two consecutive checks with drift above drift_threshold the stream switches to
+ * plain ERX (re-initialised from the next line) for good.  The plain-ERX detector used after
+ * a switch is allocated at creation (256 lines per pass), so a switch allocates nothing.
+ * The detector keeps a pointer to net, which must outlive it. */
 typedef struct erx_sdet erx_sdet;
 ERX_API erx_sdet *erx_surrogate_detector_create(erx_surr *net, int pixels, float momentum,
                                                 float drift_threshold, int check_every);

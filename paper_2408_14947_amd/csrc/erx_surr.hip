@@ -352,7 +352,7 @@ struct erx_sdet {
     int drift_run = 0;
     long long checks = 0, drifts = 0, switched_at = -1;
     erx_ctx* monitor = nullptr;  // plain ERX on the check lines
-    erx_ctx* plain = nullptr;
+    erx_ctx* plain = nullptr;    // plain ERX after a switch (made up front: switching allocates nothing)
     hipStream_t stream = nullptr;
     Erx16 erx;                   // the surrogate's projected stream
     Erx16 mon16;                 // the surrogate on the check lines
@@ -591,8 +591,12 @@ erx_sdet* erx_surrogate_detector_create(erx_surr* net, int pixels, float momentu
     c.block_lines = 1;
     c.scan_lines = 1;
     sd->monitor = erx_create_ex(&c);
-    bool ok = sd->monitor && hipStreamCreateWithFlags(&sd->stream, hipStreamNonBlocking) == hipSuccess &&
-              erx_set_stream(sd->monitor, sd->stream) == ERX_OK &&
+    erx_config cp;
+    erx_config_default(&cp, net->b, pixels, momentum);
+    cp.block_lines = 256;  // lines per pass of the fallback detector
+    sd->plain = erx_create_ex(&cp);
+    bool ok = sd->monitor && sd->plain && hipStreamCreateWithFlags(&sd->stream, hipStreamNonBlocking) == hipSuccess &&
+              erx_set_stream(sd->monitor, sd->stream) == ERX_OK && erx_set_stream(sd->plain, sd->stream) == ERX_OK &&
               hipMalloc(&sd->dummy, (size_t)pixels * 256 * sizeof(float)) == hipSuccess &&
               hipMalloc(&sd->mscore, (size_t)pixels * sizeof(float)) == hipSuccess &&
               sd->erx.ensure(256, pixels) == hipSuccess && sd->mon16.ensure(1, pixels) == hipSuccess;
@@ -677,12 +681,7 @@ int erx_surrogate_detector_push(erx_sdet* sd, const float* lines, int n)
             const bool drift = !(med <= sd->theta);  // NaN counts as drift
             sd->drifts += drift ? 1 : 0;
             sd->drift_run = drift ? sd->drift_run + 1 : 0;
-            if (sd->drift_run >= 2) {
-                erx_config c;
-                erx_config_default(&c, b, p, sd->alpha);
-                sd->plain = erx_create_ex(&c);
-                if (!sd->plain) return ERX_ENOMEM;
-                if (erx_set_stream(sd->plain, s) != ERX_OK) return ERX_EDEVICE;
+            if (sd->drift_run >= 2) {  // the fallback detector starts from the next line
                 sd->active = false;
                 sd->switched_at = last + 1;
             }
