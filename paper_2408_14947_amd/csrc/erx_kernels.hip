@@ -178,6 +178,42 @@ template <> struct G4<ERX_GRAM_FP32> {
             }
         }
     }
+    // Wave 3 of a full diagonal macro tile: tile (3, 3) into acc[0] and tile
+    // (0, 3) into acc[1] (the panel is shared, so row tile 3 is also the column
+    // operand of both)
+    static __device__ __forceinline__ void chunk_pair(const uint32_t* Rt, int c, int g, int kend, f4* acc)
+    {
+        const int r3 = 48 + c, r0 = c;
+        auto rd = [&](int u, f4& a3, f4& a0) __attribute__((always_inline)) {
+            const int qd = (u >> 2) + g;
+            a3 = *(const f4*)&Rt[r3 * 64 + 4 * (qd ^ g4_sw(r3))];
+            a0 = *(const f4*)&Rt[r0 * 64 + 4 * (qd ^ g4_sw(r0))];
+        };
+        auto mul = [&](const f4& a3, const f4& a0) __attribute__((always_inline)) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                acc[0] = mfma(a3[st], a3[st], acc[0]);
+                acc[1] = mfma(a0[st], a3[st], acc[1]);
+            }
+        };
+        if (kend == 64) {
+            f4 a3[4], a0[4];
+            rd(0, a3[0], a0[0]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < 3) rd(16 * (k + 1), a3[k + 1], a0[k + 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                mul(a3[k], a0[k]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            for (int u = 0; u < kend; u += 16) {
+                f4 a3, a0;
+                rd(u, a3, a0);
+                mul(a3, a0);
+            }
+        }
+    }
 };
 template <int PREC> struct G4H {
     typedef typename LP<PREC>::v4 v4;
@@ -343,9 +379,14 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
     // Column tiles of this wave: 4MJ + qoff + q for q < nq.  In a diagonal
     // macro tile wave w needs only the tiles on and right of the diagonal
     // (qoff = w): the tiles below it are neither computed nor stored.
+    // In a full diagonal macro tile (FP32) tile (0, 3) moves from wave 0 to
+    // wave 3, so that the waves carry 3, 3, 2 and 2 tiles instead of 4, 3, 2, 1.
     const int qoff = dg ? w : 0;
     const int ncol = (NT - 4 * MJ) < 4 ? (NT - 4 * MJ) : 4;
-    const int nq = __builtin_amdgcn_readfirstlane(ncol - qoff > 0 ? ncol - qoff : 1);
+    const bool split = dg && PREC == ERX_GRAM_FP32 && ncol == 4;
+    const bool pairw = split && w == 3;  // wave 3: tiles (3, 3) and (0, 3)
+    const int nq = __builtin_amdgcn_readfirstlane(pairw ? 2 : (split && w == 0) ? 3
+                                                                   : (ncol - qoff > 0 ? ncol - qoff : 1));
     int tbits = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) tbits |= (rowok && q < nq) ? (1 << q) : 0;
@@ -373,11 +414,20 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         const uint32_t* Cb = dg ? Rb : (const uint32_t*)(Ct + (it & 1) * G::WORDS);
         if (rowok) {
             const int kend = (p - k0) < 64 ? (p - k0) : 64;
-            switch (nq) {
-            case 1: G::template chunk<1>(Rb, Cb, w, c, g, kend, qoff, acc); break;
-            case 2: G::template chunk<2>(Rb, Cb, w, c, g, kend, qoff, acc); break;
-            case 3: G::template chunk<3>(Rb, Cb, w, c, g, kend, qoff, acc); break;
-            default: G::template chunk<4>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+            bool paired = false;
+            if constexpr (PREC == ERX_GRAM_FP32 && DG) {
+                if (pairw) {
+                    G::chunk_pair(Rb, c, g, kend, acc);
+                    paired = true;
+                }
+            }
+            if (!paired) {
+                switch (nq) {
+                case 1: G::template chunk<1>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+                case 2: G::template chunk<2>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+                case 3: G::template chunk<3>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+                default: G::template chunk<4>(Rb, Cb, w, c, g, kend, qoff, acc); break;
+                }
             }
         }
         if (((k0 + 64) % G::FLUSH) == 0 || k0 + 64 >= p) {
@@ -440,14 +490,16 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (!(tbits & (1 << q))) continue;
-        const double scol = bsum_s[64 + 16 * (q + qoff) + c];
+        const int rt = (pairw && q == 1) ? 0 : w;  // row and column tile within the macro tile
+        const int ct = pairw ? 3 : qoff + q;
+        const double scol = bsum_s[64 + 16 * ct + c];
         double o[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double srho = bsum_s[16 * w + 4 * g + i];
+            const double srho = bsum_s[16 * rt + 4 * g + i];
             o[i] = (S[q][i] - srho * scol * inv_p) * inv_p1;
         }
-        double* dst = ls + tile_u(I, 4 * MJ + qoff + q, NT) * 256 + lane * 4;
+        double* dst = ls + tile_u(4 * MI + rt, 4 * MJ + ct, NT) * 256 + lane * 4;
         *(double2*)dst = double2{o[0], o[1]};
         *(double2*)(dst + 2) = double2{o[2], o[3]};
     }
