@@ -602,11 +602,30 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
     GLB double* state = glb(d.state);
     double cv = state[e];
     const int nseg = (d.n + P.seg - 1) / P.seg;
-    for (int gs = 0; gs < nseg; ++gs) {
-        carry[(size_t)(d.seg0 + gs) * E + e] = cv;
-        const int l0 = gs * P.seg;
-        const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
-        cv = seg_decay(d.t0, l0, l1, d.alpha) * cv + stats[(size_t)(d.line0 + l1 - 1) * E + e];
+    // decay over a whole segment that does not hold the stream's first line
+    // (the same product as seg_decay); other segments take seg_decay
+    const double full = seg_decay(1, 0, P.seg, d.alpha);
+    // the segment end values are read eight at a time ahead of the serial chain
+    constexpr int U = 8;
+    for (int g0 = 0; g0 < nseg; g0 += U) {
+        double ev[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int gs = g0 + u < nseg ? g0 + u : nseg - 1;
+            const int l1 = (gs * P.seg + P.seg) < d.n ? (gs * P.seg + P.seg) : d.n;
+            ev[u] = stats[(size_t)(d.line0 + l1 - 1) * E + e];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int gs = g0 + u;
+            if (gs < nseg) {
+                carry[(size_t)(d.seg0 + gs) * E + e] = cv;
+                const int l0 = gs * P.seg;
+                const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
+                const bool whole = l1 - l0 == P.seg && d.t0 + l0 > 0;
+                cv = (whole ? full : seg_decay(d.t0, l0, l1, d.alpha)) * cv + ev[u];
+            }
+        }
     }
     state[e] = cv;
 }
