@@ -56,17 +56,30 @@ def _csv_rows(d, suffix):
     return rows
 
 
-def summarize_trace(d, command):
+def summarize_trace(d, command, workload=WORKLOAD):
     """Markdown table of rocprofv3's kernel statistics (--kernel-trace --stats -f csv)."""
     rows = _csv_rows(d, "kernel_stats.csv")
     if not rows:
         sys.exit(f"no *kernel_stats.csv under {d}")
-    out = ["# Kernel trace: " + WORKLOAD, "", "Command (repository root on the GPU host):", "",
+    out = ["# Kernel trace: " + workload, "", "Command (repository root on the GPU host):", "",
            "```", command, "```", "",
            f"Kernel source sha256[:16] = {kernel_source_hash()}", "",
            "| kernel | calls | total_ms | avg_us | min_us | max_us | pct |", "|---|---|---|---|---|---|---|"]
+    # several instantiations of one kernel keep their template arguments apart
+    shorts = [short_kernel(r["Name"]) for r in rows]
+    dup = {k for k in shorts if k and shorts.count(k) > 1}
+
+    def label(name):
+        k = short_kernel(name)
+        if k is None:
+            return name[:60] + ("..." if len(name) > 60 else "")
+        if k in dup:
+            m = re.search(r"erx::k_\w+?<([^>]*)>", name)
+            return f"{k}<{m.group(1).replace(' ', '')}>" if m else k
+        return k
+
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        nm = short_kernel(r["Name"]) or (r["Name"][:60] + ("..." if len(r["Name"]) > 60 else ""))
+        nm = label(r["Name"])
         out.append(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                    f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
@@ -463,13 +476,14 @@ def main():
     ap.add_argument("--rocprof-summary", nargs="+", metavar="DIR",
                     help="no GPU: print a markdown summary of rocprofv3 CSV output under DIR(s)")
     ap.add_argument("--rocprof-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--rocprof-workload", default=WORKLOAD, help="workload named in a trace summary's title")
     args = ap.parse_args()
     if args.rocprof_summary:
         if args.calibrate_copy:
             print(summarize_counters(args.rocprof_summary, args.rocprof_command, args.calibrate_copy,
                                      args.block_lines))
         else:
-            print(summarize_trace(args.rocprof_summary[0], args.rocprof_command))
+            print(summarize_trace(args.rocprof_summary[0], args.rocprof_command, args.rocprof_workload))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
