@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
         // addresses computed from them would stay live across it and spill.
         int tl = tid;
         __asm__ volatile("" : "+v"(tl));
-        const int lane = tl & 63, g = lane >> 4, c = lane & 15, band0 = 4 * g;
+        const int lane = tl & 63, g = lane >> 4, c = lane & 15;
         GLB float* out = glb(d.out + (size_t)l * p);
         __syncthreads();  // the previous line's reads of the buffer are done
         lstore(tl);
@@ -470,13 +470,16 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
         }
         __syncthreads();
 
-        // ---- scores (lane (g, c): bands 4g..4g+3 of pixel c of a tile)
+        // ---- scores (lane (g, c): bands g, 4+g, 8+g, 12+g of pixel c of a tile,
+        //      so that product k contracts bands 4k..4k+3 and the products past
+        //      the stream's band count are skipped)
         const bool bad = bad_s != 0;
+        const int nkb = (b + 3) >> 2;  // 4-band groups holding real bands
         f4 xt, m4;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            xt[i] = (float)xt_s[c * 17 + 4 * g + i];  // X^T[4g+i][c]
-            m4[i] = mu_s[4 * g + i];
+            xt[i] = (float)xt_s[c * 17 + 4 * i + g];  // X[c][4i+g]
+            m4[i] = mu_s[4 * i + g];
         }
         double s1 = 0.0, s2 = 0.0;
         // two tiles per step as in the Gram: next reads in flight, chains interleaved
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
             const int px = 16 * tt + c;
             const int row = (px < p ? px : p - 1) * b;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = lx[row + (band0 + q < b ? band0 + q : b - 1)];
+            for (int q = 0; q < 4; ++q) v[q] = lx[row + (4 * q + g < b ? 4 * q + g : b - 1)];
         };
         // Reads outside the line were clamped to an element of it, so every
         // residual entry is finite: padded bands meet zero columns of X and
@@ -519,8 +522,10 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
             f4 y0 = f4{0.f, 0.f, 0.f, 0.f}, y1 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {  // L^{-1} r of pixel c, rows 4g..4g+3
-                y0 = mfma(xt[k], r0[k], y0);
-                y1 = mfma(xt[k], r1[k], y1);
+                if (k < nkb) {
+                    y0 = mfma(xt[k], r0[k], y0);
+                    y1 = mfma(xt[k], r1[k], y1);
+                }
             }
             emit(tt, y0);
             emit(tt + 4, y1);
