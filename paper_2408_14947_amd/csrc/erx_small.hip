@@ -392,12 +392,20 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
         // LDS addresses are clamped into the line (pixel p-1, band b-1) rather than
         // selected: a select on the address becomes a branch around each read and a
         // wait after it.  Values outside the line are masked where they are used.
-        const int cb = c < b ? c : b - 1;
-        const double sh = (c < b) ? (double)Raw1<DT>::cvt(lx[cb]) : 0.0;
+        // Narrow streams (b <= 8) pack G = 16 / bp pixel groups into the 16 band
+        // rows of a tile (bp = 4 or 8, group j in rows j*bp..j*bp+bp-1): the
+        // diagonal bp x bp blocks of the product are the Gram sums of the groups'
+        // pixels and add up to the line's, with G times fewer products.
+        const int lg = b <= 4 ? 2 : (b <= 8 ? 3 : 4);
+        const int bp = 1 << lg, G = 16 >> lg, SP = 16 * G;  // SP pixels per tile
+        const int band = c & (bp - 1), grp = c >> lg;
+        const int nst = (p + SP - 1) / SP;
+        const int cb = band < b ? band : b - 1;
+        const double sh = (band < b) ? (double)Raw1<DT>::cvt(lx[cb]) : 0.0;
         auto graw = [&](int tt, RT (&v)[4]) __attribute__((always_inline)) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int px = 16 * tt + 4 * g + i;
+                const int px = SP * tt + 16 * grp + 4 * g + i;
                 v[i] = lx[(px < p ? px : p - 1) * b + cb];
             }
         };
@@ -405,8 +413,8 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
             d4 xv;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int px = 16 * tt + 4 * g + i;
-                xv[i] = (px < p && c < b) ? (double)Raw1<DT>::cvt(v[i]) - sh : 0.0;
+                const int px = SP * tt + 16 * grp + 4 * g + i;
+                xv[i] = (px < p && band < b) ? (double)Raw1<DT>::cvt(v[i]) - sh : 0.0;
             }
             return xv;
         };
@@ -415,7 +423,7 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
         RT ra[4], rb[4];
         graw(w, ra);
         graw(w + 4, rb);
-        for (int tt = w; tt < ntile; tt += 8) {
+        for (int tt = w; tt < nst; tt += 8) {
             const d4 x0 = gval(tt, ra), x1 = gval(tt + 4, rb);
             graw(tt + 8, ra);
             graw(tt + 12, rb);
@@ -437,15 +445,28 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
         // ---- line statistics, moving averages and factorisation (wave 0)
         if (w == 0) {
             const double a = (t == 0) ? 1.0 : d.alpha;
-            const double bc = (red_s[0][256 + c] + red_s[1][256 + c]) + (red_s[2][256 + c] + red_s[3][256 + c]);
+            // sums over the four waves and the G pixel groups (band r of group j
+            // is row j*bp + r of the waves' products)
+            auto bsum = [&](int r) __attribute__((always_inline)) {
+                double v = 0.0;
+                for (int j = 0; j < G; ++j)
+                    v += (red_s[0][256 + j * bp + r] + red_s[1][256 + j * bp + r]) +
+                         (red_s[2][256 + j * bp + r] + red_s[3][256 + j * bp + r]);
+                return v;
+            };
+            const double bc = c < bp ? bsum(c) : 0.0;
             double aa[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 4 * g + i;
-                const double br =
-                    (red_s[0][256 + row] + red_s[1][256 + row]) + (red_s[2][256 + row] + red_s[3][256 + row]);
-                const double s = (red_s[0][row * 16 + c] + red_s[1][row * 16 + c]) +
-                                 (red_s[2][row * 16 + c] + red_s[3][row * 16 + c]);
+                double s = 0.0, br = 0.0;
+                if (row < bp && c < bp) {
+                    br = bsum(row);
+                    for (int j = 0; j < G; ++j) {
+                        const int e = (j * bp + row) * 16 + j * bp + c;
+                        s += (red_s[0][e] + red_s[1][e]) + (red_s[2][e] + red_s[3][e]);
+                    }
+                }
                 const double kh = (s - br * bc * inv_p) * inv_p1;
                 Kst[i] = (1.0 - a) * Kst[i] + a * kh;
                 double av = Kst[i];
