@@ -1059,7 +1059,10 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
 // pixel data of the next column is prefetched into registers the same way.
 // ============================================================================
 template <int NT, int DT, bool VEC>
-__global__ __launch_bounds__(256, 2) void k_score(const Pass P, const float* __restrict__ Mt,
+// three workgroups per CU (three waves per SIMD) up to 14 tiles: at 14 a few
+// registers spill and the extra wave still wins (1.92 -> 1.86 ms at 224 bands);
+// above 14 tiles the spills grow, so two
+__global__ __launch_bounds__(256, NT <= 14 ? 3 : 2) void k_score(const Pass P, const float* __restrict__ Mt,
                                                const float* __restrict__ mu32, int ngrp)
 {
     constexpr int NTL = NT * (NT + 1) / 2;
