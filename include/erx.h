@@ -80,7 +80,9 @@ typedef struct erx_config {
     double fp64_cond_threshold; /* 0 (default): every line is factored in FP64.  > 0: lines are
                                    factored in FP32 and those whose 1-norm condition estimate of
                                    K_t + eps I exceeds this (or that meet a non-positive pivot) are
-                                   re-factored in FP64; +inf: FP32 only */
+                                   re-factored in FP64; +inf: FP32 only, and a line that
+                                   meets a non-positive pivot is reported not positive
+                                   definite (ERX_ENOTPD, NaN scores) */
     int normalise;   /* 1: also produce line-normalised scores (erx_scores_normalised) */
     int block_lines; /* lines per device pass (scratch is sized for it); default 2048 */
     int scan_lines;  /* lines per segment of the chunked moving-average scan; default 64 */

@@ -52,6 +52,9 @@ struct Pass {
 hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s);
+// fp64 = 1: FP64 factorisation of every line (force = 1) or of the lines the
+// FP32 pass flagged (force = 0).  fp64 = 0: FP32 factorisation; force = 1
+// there means no FP64 pass follows, so a failed pivot marks the line not PD.
 hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,
                        float* Mt, float* mu32, int* flags, float* cond, double thr, int want_cond,
                        unsigned long long* ctr, hipStream_t s);

@@ -1031,6 +1031,11 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
         if (!FB) {
             f = 0;
             if (fail || threshold <= 0.0 || (want_cond && (double)est > threshold)) f |= FLAG_NEED_FP64;
+            // force on the FP32 instantiation: no FP64 pass follows, so a failed pivot is final
+            if (fail && force) {
+                f |= FLAG_NOTPD;
+                atomicAdd(&counters[1], 1ull);
+            }
             cond[line] = fail ? __builtin_inff() : (want_cond ? est : 0.f);
             if (!(f & FLAG_NEED_FP64) && fin) atomicMax((unsigned int*)&counters[2], __float_as_uint(est));
         } else {
@@ -1322,7 +1327,7 @@ hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double*
     if (fp64)
         chol_dispatch<double>(seq, NT, P, stats, carry, Mt, mu32, flags, cond, thr, want_cond, force, ctr, s);
     else
-        chol_dispatch<float>(seq, NT, P, stats, carry, Mt, mu32, flags, cond, thr, want_cond, 0, ctr, s);
+        chol_dispatch<float>(seq, NT, P, stats, carry, Mt, mu32, flags, cond, thr, want_cond, force, ctr, s);
     return hipGetLastError();
 }
 

@@ -83,7 +83,8 @@ hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, d
     if ((e = T(K_SCAN_CARRY, [&] { return launch_scan_carry(P, NT, stats, carry, s); })) != hipSuccess) return e;
     if (thr > 0.0) {
         e = T(K_CHOL32, [&] {
-            return launch_chol(0, 0, P, NT, stats, carry, Mt, mu32, flags, cond, thr, want_cond, ctr, s);
+            return launch_chol(0, fp64_pass ? 0 : 1, P, NT, stats, carry, Mt, mu32, flags, cond, thr, want_cond,
+                               ctr, s);
         });
         if (e != hipSuccess) return e;
         if (fp64_pass) {

@@ -289,6 +289,53 @@ def test_not_positive_definite(erx):
         det.scores_host(allow_notpd=False)
 
 
+def test_not_positive_definite_fp32_only(erx):
+    """With fp64_cond_threshold = inf no FP64 pass follows the FP32 factorisation, so a
+    line that meets a non-positive pivot there is the final word: it is flagged not PD,
+    counted, and erx_scores reports ERX_ENOTPD (the same lines as the oracle)."""
+    log("not positive definite lines, FP32 factorisation only")
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((6, 40, 8)).astype(np.float32)
+    X[3:, :, 2] = 0.5
+    got, det = run_gpu(erx, torch.from_numpy(X), momentum=1.0, ridge=0.0, fp64_cond_threshold=float("inf"))
+    want = oracle.run(X, 1.0, 0.0)
+    cond, flags = det.line_info()
+    assert list((flags & erx.FLAG_NOTPD) > 0) == list(want["notpd"].astype(bool))
+    assert det.stats()["notpd"] == int(want["notpd"].sum())
+    assert np.isnan(got[3:]).all() and np.isfinite(got[:3]).all()
+    with pytest.raises(erx.ErxError) as e:
+        det.scores_host(allow_notpd=False)
+    assert e.value.code == erx.ERX_ENOTPD
+
+
+def test_minimal_c_abi_create_push_scores(erx):
+    """The three calls of the minimal boundary, exactly: erx_create(bands, pixels,
+    momentum) -> erx_push_lines(handle, lines, n) with FP32 lines in HOST memory ->
+    erx_scores(handle, out) into a host buffer, called through ctypes; two pushes."""
+    import ctypes as C
+    log("minimal C ABI: erx_create / erx_push_lines / erx_scores (host buffers)")
+    lib = erx.load()
+    b, p, T = 36, 150, 90
+    scene = datagen.make_scene(24, 0, b, p, T)
+    X = np.ascontiguousarray(datagen.lines(scene, 0, T)[0].numpy())
+    h = lib.erx_create(b, p, C.c_float(0.1))
+    assert h, erx.last_error()
+    try:
+        got = np.full((T, p), np.nan, np.float32)
+        for a, c in [(0, 61), (61, T)]:
+            chunk = np.ascontiguousarray(X[a:c])
+            assert lib.erx_push_lines(h, C.c_void_p(chunk.ctypes.data), c - a) == erx.ERX_OK, erx.last_error()
+            outv = np.empty((c - a, p), np.float32)
+            assert lib.erx_scores(h, C.c_void_p(outv.ctypes.data)) == erx.ERX_OK, erx.last_error()
+            got[a:c] = outv
+    finally:
+        lib.erx_destroy(h)
+    want = oracle.run(X, 0.1, 1e-5)["delta"]
+    err = rel_err(got, want)
+    log(f"  max err {err.max():.3e}")
+    assert err.max() <= TOL
+
+
 def test_nan_input_propagates_forward(erx):
     log("NaN input")
     sc = datagen.make_scene(22, 0, 20, 64, 12)
