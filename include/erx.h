@@ -289,6 +289,41 @@ ERX_API int erx_surrogate_detector_status(const erx_sdet *sd, int *active, long 
                                           long long *drifts, long long *switched_at);
 ERX_API void erx_surrogate_detector_destroy(erx_sdet *sd);
 
+/* ---------------------------------------------------------------------------------------
+ * Allocation-free push, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It computes what
+ * erx_create_ex + erx_push_lines_ex + erx_scores_device compute for one stream (same
+ * kernels, same results), with no handle: the caller owns the lines, the scores and the
+ * stream's moving-average state, and the library's intermediate buffers (per-line
+ * statistics, scan carries, inverse factors) live in one static device array of
+ * ERX_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.  No hipMalloc, hipFree or
+ * allocating library routine is called; the first call on a device looks up the array's
+ * address once (hipGetSymbolAddress), so make one call on each device before capturing.
+ *
+ *   cfg      as for erx_create_ex; normalise must be 0.  block_lines caps the lines per
+ *            device pass; the scratch caps it further (152 lines at 224 bands, 84 at
+ *            304 with scan_lines 64), and longer pushes run in several passes.
+ *   state    device buffer of E = 256*NT*(NT+1)/2 + 16*NT doubles, NT = ceil(bands/16): the
+ *            background after the stream's last line, in the library's packed layout
+ *            (opaque).  Read and rewritten by the call; with t0 = 0 its contents are ignored.
+ *   t0       lines the stream absorbed before this call (0: the first line initialises the
+ *            background); the caller adds n after each call.
+ *   lines    device buffer [n][pixels][bands] in cfg->dtype, aligned to its element size.
+ *   out      device buffer [n][pixels] FP32 receiving the distances delta.
+ *   hip_stream  stream the work is enqueued on (NULL: the default stream).  Returns once
+ *            enqueued and never waits for the device.
+ *
+ * Errors: ERX_EINVAL for invalid arguments (bands beyond ERX_MAX_BANDS, the largest size the
+ * scratch is laid out for; pixels < 2; n < 1; normalise = 1; a buffer that is not device
+ * memory ...), with nothing enqueued; ERX_EDEVICE when the scratch address cannot be found
+ * or a launch fails.  Lines whose covariance is not positive definite get NaN scores and
+ * are not reported (that would need a wait).  Every call on a GPU shares that GPU's scratch
+ * and it keeps the last call's contents: calls that overlap on one GPU (different streams,
+ * several threads) race and must be serialised, e.g. on one stream. */
+#define ERX_NOALLOC_SCRATCH_BYTES (48u << 20)
+ERX_API int erx_push_lines_noalloc(const erx_config *cfg, double *state, long long t0, const void *lines, int n,
+                                   float *out, void *hip_stream);
+
 /* Wait for all work enqueued on the handle's stream. */
 ERX_API int erx_synchronize(erx_ctx *h);
 

@@ -34,7 +34,7 @@ EXPORTS = (
     "erx_surrogate_get_params", "erx_surrogate_scores", "erx_surrogate_train_step",
     "erx_surrogate_grads", "erx_surrogate_destroy", "erx_surrogate_detector_create",
     "erx_surrogate_detector_push", "erx_surrogate_detector_scores", "erx_surrogate_detector_status",
-    "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup",
+    "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup", "erx_push_lines_noalloc",
 )
 SURR_K, SURR_HIDDEN = 16, 64
 
@@ -125,6 +125,7 @@ def load(path: str = LIB_PATH):
         "erx_surrogate_detector_destroy": (None, [vp]),
         "erx_autotune": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
         "erx_tune_lookup": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
+        "erx_push_lines_noalloc": (ip, [C.POINTER(Config), vp, C.c_longlong, vp, ip, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -403,8 +404,44 @@ class Batch:
         _check(self._lib.erx_batch_synchronize(self._h))
 
 
+NOALLOC_SCRATCH_BYTES = 48 << 20
+
+
+def noalloc_state_entries(bands: int) -> int:
+    """Doubles of the caller-owned stream state of push_lines_noalloc."""
+    nt = (int(bands) + 15) // 16
+    return 256 * nt * (nt + 1) // 2 + 16 * nt
+
+
+def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge: float = 1e-5,
+                       dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
+                       block_lines: int = 2048, scan_lines: int = 64, cond_estimate: int = -1,
+                       stream: Optional[int] = -1) -> int:
+    """erx_push_lines_noalloc: score lines [n, pixels, bands] (device tensor) into out
+    [n, pixels] (device float32) with the caller-owned FP64 state (device tensor of
+    noalloc_state_entries(bands) doubles); t0 = lines the stream absorbed before.
+    Returns t0 + n.  stream: hipStream_t, -1 = torch's current stream."""
+    lib = load()
+    n, p, b = (int(v) for v in lines.shape)
+    cfg = Config()
+    lib.erx_config_default(C.byref(cfg), b, p, float(momentum))
+    cfg.ridge = float(ridge)
+    cfg.dtype = DTYPES[dtype]
+    cfg.precision = PRECISIONS[precision]
+    cfg.fp64_cond_threshold = float(fp64_cond_threshold)
+    cfg.block_lines = int(block_lines)
+    cfg.scan_lines = int(scan_lines)
+    cfg.cond_estimate = int(cond_estimate)
+    if stream == -1:
+        stream = _torch_stream()
+    _check(lib.erx_push_lines_noalloc(C.byref(cfg), C.c_void_p(_ptr(state)), int(t0), C.c_void_p(_ptr(lines)),
+                                      n, C.c_void_p(_ptr(out)), C.c_void_p(stream)))
+    return int(t0) + n
+
+
 __all__ = ["Detector", "Batch", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
-           "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "MAX_BANDS"]
+           "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "MAX_BANDS", "push_lines_noalloc",
+           "noalloc_state_entries", "NOALLOC_SCRATCH_BYTES"]
 
 
 # ---------------------------------------------------------------------------

@@ -100,3 +100,25 @@ def test_tune_cache_lookup(tmp_path):
     assert e.value.code == erx.ERX_EINVAL
     with pytest.raises(erx.ErxError):
         erx.autotune(224, 1024, nstreams=0)  # rejected before any device work
+
+
+def test_noalloc_rejects_invalid_arguments_before_device_work():
+    """erx_push_lines_noalloc checks its arguments on the host before any HIP call,
+    so these return ERX_EINVAL on a machine without a GPU."""
+    erx, lib = _lib()
+    dummy = C.c_void_p(16)  # never dereferenced: every case fails before device work
+    cases = [dict(bands=305), dict(bands=0), dict(pixels=1), dict(momentum=0.0), dict(normalise=1),
+             dict(dtype=5), dict(precision=9), dict(block_lines=0), dict(scan_lines=0)]
+    for case in cases:
+        cfg = erx.Config()
+        lib.erx_config_default(C.byref(cfg), 16, 32, 0.1)
+        for k, v in case.items():
+            setattr(cfg, k, v)
+        assert lib.erx_push_lines_noalloc(C.byref(cfg), dummy, 0, dummy, 4, dummy, None) == erx.ERX_EINVAL, case
+    cfg = erx.Config()
+    lib.erx_config_default(C.byref(cfg), 16, 32, 0.1)
+    assert lib.erx_push_lines_noalloc(C.byref(cfg), dummy, 0, dummy, 0, dummy, None) == erx.ERX_EINVAL
+    assert "n must be" in erx.last_error()
+    assert lib.erx_push_lines_noalloc(C.byref(cfg), dummy, -1, dummy, 4, dummy, None) == erx.ERX_EINVAL
+    assert lib.erx_push_lines_noalloc(None, dummy, 0, dummy, 4, dummy, None) == erx.ERX_EINVAL
+    assert erx.noalloc_state_entries(224) == 256 * 105 + 224
