@@ -66,6 +66,15 @@ enum {
     ERX_GRAM_FP16 = 2  /* FP16 inputs on the matrix cores, FP32 accumulate */
 };
 
+/* arithmetic of the score product L^{-1}(x - mu) (Sec. III-D) */
+enum {
+    ERX_SCORE_SPLIT16 = 0, /* default: operands scaled by powers of two and split into two FP16
+                              halves, three FP16 matrix-core products per tile with FP32
+                              accumulation (FP32-class accuracy); lines whose residuals span
+                              more than the split can hold are scored again in FP32 */
+    ERX_SCORE_FP32 = 1     /* FP32 matrix cores */
+};
+
 typedef struct erx_ctx erx_ctx;
 
 typedef struct erx_config {
@@ -88,13 +97,14 @@ typedef struct erx_config {
     int scan_lines;  /* lines per segment of the chunked moving-average scan; default 64 */
     int cond_estimate; /* 1-norm condition estimate per line: -1 (default) only when it decides
                           the FP64 re-factor (0 < threshold < inf), 0 never, 1 always */
+    int score_arith;   /* ERX_SCORE_SPLIT16 (default) or ERX_SCORE_FP32 */
 } erx_config;
 
 #define ERX_MAX_BANDS 304
 
 /* Fill *cfg with defaults: ridge 1e-5, warmup 0, F32 input, FP32 Gram,
  * threshold 0 (FP64 factorisation), no normalisation, block_lines 2048,
- * scan_lines 64, cond_estimate -1. */
+ * scan_lines 64, cond_estimate -1, split-FP16 score. */
 ERX_API void erx_config_default(erx_config *cfg, int bands, int pixels, float momentum);
 
 /* Create a detector on the current HIP device.  Returns NULL on error

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "liberx.so")
 ERX_OK, ERX_EINVAL, ERX_ENOMEM, ERX_EDEVICE, ERX_ENOTPD, ERX_ESTATE = 0, -1, -2, -3, -4, -5
 DTYPES = {"f32": 0, "f16": 1, "u16": 2}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
-FLAG_NEED_FP64, FLAG_FP64_DONE, FLAG_NOTPD = 1, 2, 4
+SCORE_ARITH = {"split16": 0, "fp32": 1}
+FLAG_NEED_FP64, FLAG_FP64_DONE, FLAG_NOTPD, FLAG_SCORE32 = 1, 2, 4, 8
 MAX_BANDS = 304
 
 # every entry point declared in include/erx.h
@@ -50,7 +51,7 @@ class Config(C.Structure):
                 ("ridge", C.c_float), ("warmup", C.c_int), ("dtype", C.c_int),
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
-                ("cond_estimate", C.c_int)]
+                ("cond_estimate", C.c_int), ("score_arith", C.c_int)]
 
 
 class TuneResult(C.Structure):
@@ -174,7 +175,8 @@ class Detector:
     def __init__(self, bands: int, pixels: int, momentum: float = 0.1, ridge: float = 1e-5,
                  dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
-                 scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1):
+                 scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
+                 score_arith: str = "split16"):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
         stream, None = a stream owned by the handle."""
         lib = load()
@@ -189,6 +191,7 @@ class Detector:
         cfg.block_lines = int(block_lines)
         cfg.scan_lines = int(scan_lines)
         cfg.cond_estimate = int(cond_estimate)
+        cfg.score_arith = SCORE_ARITH[score_arith]
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
         self._lib = lib
@@ -311,7 +314,7 @@ class Batch:
     def __init__(self, bands, pixels, momentum, ridge: float = 1e-5, dtype: str = "f32",
                  precision: str = "fp32",
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
-                 scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True,
+                 scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True, score_arith: str = "split16",
                  stream: Optional[int] = -1, small_path: int = -1):
         lib = load()
         self.bands = [int(x) for x in bands]
@@ -329,6 +332,7 @@ class Batch:
         cfg.block_lines = int(block_lines)
         cfg.scan_lines = int(scan_lines)
         cfg.cond_estimate = int(cond_estimate)
+        cfg.score_arith = SCORE_ARITH[score_arith]
         b = (C.c_int * ns)(*self.bands)
         p = (C.c_int * ns)(*self.pixels)
         m = (C.c_float * ns)(*[float(x) for x in momentum])
@@ -416,7 +420,7 @@ def noalloc_state_entries(bands: int) -> int:
 def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge: float = 1e-5,
                        dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
                        block_lines: int = 2048, scan_lines: int = 64, cond_estimate: int = -1,
-                       stream: Optional[int] = -1) -> int:
+                       stream: Optional[int] = -1, score_arith: str = "split16") -> int:
     """erx_push_lines_noalloc: score lines [n, pixels, bands] (device tensor) into out
     [n, pixels] (device float32) with the caller-owned FP64 state (device tensor of
     noalloc_state_entries(bands) doubles); t0 = lines the stream absorbed before.
@@ -432,6 +436,7 @@ def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge:
     cfg.block_lines = int(block_lines)
     cfg.scan_lines = int(scan_lines)
     cfg.cond_estimate = int(cond_estimate)
+    cfg.score_arith = SCORE_ARITH[score_arith]
     if stream == -1:
         stream = _torch_stream()
     _check(lib.erx_push_lines_noalloc(C.byref(cfg), C.c_void_p(_ptr(state)), int(t0), C.c_void_p(_ptr(lines)),
@@ -440,7 +445,7 @@ def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge:
 
 
 __all__ = ["Detector", "Batch", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
-           "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "MAX_BANDS", "push_lines_noalloc",
+           "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "FLAG_SCORE32", "MAX_BANDS", "SCORE_ARITH", "push_lines_noalloc",
            "noalloc_state_entries", "NOALLOC_SCRATCH_BYTES"]
 
 

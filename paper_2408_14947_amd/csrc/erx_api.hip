@@ -44,6 +44,7 @@ struct erx_ctx {
     double* carry = nullptr;   // [nseg][E] background entering each scan segment
     float* Mt = nullptr;       // [C][NTL][256] inverse-factor tiles
     float* mu32 = nullptr;     // [C][bpad] background mean per line
+    float* mscale = nullptr;   // [C] max |L^{-1}| per line (split-FP16 score)
     unsigned long long* ctr = nullptr;  // fp64 re-factors, not-PD lines, max cond (float bits)
     int* flags = nullptr;      // [cap] per line of the last push
     float* cond = nullptr;     // [cap]
@@ -64,7 +65,7 @@ namespace {
 
 void free_all(erx_ctx* h)
 {
-    void* ptrs[] = {h->state, h->stats, h->carry, h->Mt, h->mu32, h->ctr, h->flags, h->cond,
+    void* ptrs[] = {h->state, h->stats, h->carry, h->Mt, h->mu32, h->mscale, h->ctr, h->flags, h->cond,
                     h->scores, h->scores_n, h->labels, h->staging};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -141,6 +142,7 @@ void erx_config_default(erx_config* cfg, int bands, int pixels, float momentum)
     cfg->block_lines = 2048;
     cfg->scan_lines = 64;
     cfg->cond_estimate = -1;
+    cfg->score_arith = ERX_SCORE_SPLIT16;
 }
 
 erx_ctx* erx_create_ex(const erx_config* cfg)
@@ -182,6 +184,10 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "cond_estimate must be -1, 0 or 1");
         return nullptr;
     }
+    if (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) {
+        fail(ERX_EINVAL, "unknown score_arith %d", c.score_arith);
+        return nullptr;
+    }
     if (c.block_lines < 1 || c.scan_lines < 1 || c.warmup < 0 || (c.normalise != 0 && c.normalise != 1)) {
         fail(ERX_EINVAL, "block_lines and scan_lines must be >= 1, warmup >= 0, normalise 0/1");
         return nullptr;
@@ -205,6 +211,7 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
          dmalloc(&h->carry, nseg * h->E * sizeof(double)) == hipSuccess &&
          dmalloc(&h->Mt, C * h->NTL * 256 * sizeof(float)) == hipSuccess &&
          dmalloc(&h->mu32, C * h->bpad * sizeof(float)) == hipSuccess &&
+         dmalloc(&h->mscale, C * sizeof(float)) == hipSuccess &&
          dmalloc(&h->ctr, 4 * sizeof(unsigned long long)) == hipSuccess;
     ok = ok && hipMemset(h->state, 0, h->E * sizeof(double)) == hipSuccess &&
          hipMemset(h->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
@@ -288,7 +295,8 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.pmax = c.pixels;
         // 4-band vector loads need b % 4 == 0 and a 4-element aligned buffer
         P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)src % (4 * esz)) == 0;
-        HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, c.precision, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
+        P.mscale = h->mscale;
+        HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, c.precision, c.score_arith, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));
         h->t += nc;

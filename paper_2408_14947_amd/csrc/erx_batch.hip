@@ -46,6 +46,7 @@ struct Group {
     double* carry = nullptr;
     float* Mt = nullptr;
     float* mu32 = nullptr;
+    float* mscale = nullptr;
     int* flags = nullptr;
     float* cond = nullptr;
     StreamDesc* d_sd[NSLOT] = {nullptr, nullptr};
@@ -81,7 +82,7 @@ void destroy_all(erx_batch* bt)
 {
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
     for (auto& g : bt->groups) {
-        void* d[] = {g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, g.d_sd[0], g.d_sd[1]};
+        void* d[] = {g.stats, g.carry, g.Mt, g.mu32, g.mscale, g.flags, g.cond, g.d_sd[0], g.d_sd[1]};
         for (void* p : d)
             if (p) (void)hipFree(p);
         for (int k = 0; k < NSLOT; ++k) {
@@ -132,7 +133,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     const erx_config& c = *common;
     if (!(c.ridge >= 0.0f) || !std::isfinite(c.ridge) || (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16) ||
         c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_FP16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
-        c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1)) {
+        c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1) ||
+        (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32)) {
         fail(ERX_EINVAL, "erx_batch_create: invalid common configuration");
         return nullptr;
     }
@@ -183,6 +185,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
              hipMalloc(&g.carry, nseg_max * g.E * sizeof(double)) == hipSuccess &&
              hipMalloc(&g.Mt, C * NTL * 256 * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.mu32, C * 16 * g.NT * sizeof(float)) == hipSuccess &&
+             hipMalloc(&g.mscale, C * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.flags, C * sizeof(int)) == hipSuccess && hipMalloc(&g.cond, C * sizeof(float)) == hipSuccess;
         for (int k = 0; k < NSLOT && ok; ++k)
             ok = hipMalloc(&g.d_sd[k], ns * sizeof(StreamDesc)) == hipSuccess &&
@@ -370,11 +373,12 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
             P.seg = seg;
             P.pmax = pmax;
             P.vec4 = vec4;
+            P.mscale = g.mscale;
             auto record = [&]() -> hipError_t {
                 hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
                                               bt->stream);
                 if (e != hipSuccess) return e;
-                return run_pass(bt->stream, P, g.NT, c.dtype, c.precision, g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, thr,
+                return run_pass(bt->stream, P, g.NT, c.dtype, c.precision, c.score_arith, g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, thr,
                                 want_cond, fp64_pass, c.normalise != 0, bt->ctr, nullptr);
             };
             if (bt->use_graphs) {

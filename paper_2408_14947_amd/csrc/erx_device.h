@@ -86,6 +86,39 @@ template <> __device__ __forceinline__ float ld1<DT_U16>(const void* X, size_t i
     return (float)glb((const uint16_t*)X)[i] * (1.0f / 65536.0f);  // exact
 }
 
+// Four consecutive elements [i, i+4) of a line as FP32, with no branches.  With
+// VEC (b % 4 == 0 and i % 4 == 0) one 8- or 16-byte load; otherwise element
+// loads, where the caller passes ok[q] = false for elements that do not exist:
+// their offset is clamped to 0 (in bounds) and the caller ignores the value.
+// A load under a divergent branch, or a use right after it, makes the compiler
+// wait for every load in flight, so callers mask the values where they use
+// them, not here.
+template <int DT, bool VEC>
+__device__ __forceinline__ f4 ldq(const void* X, size_t i, int b_left)
+{
+    f4 v;
+    if (VEC) {
+        if (DT == DT_F32) {
+            v = *(const GLB f4*)glb((const float*)X + i);
+        } else if (DT == DT_F16) {
+            const u2v uv = *(const GLB u2v*)glb((const __half*)X + i);
+            const uint2 u = make_uint2(uv.x, uv.y);
+            const float2 a = __half22float2(*(const __half2*)&u.x), c = __half22float2(*(const __half2*)&u.y);
+            v = f4{a.x, a.y, c.x, c.y};
+        } else {
+            const u2v u = *(const GLB u2v*)glb((const uint16_t*)X + i);
+            const float sc = 1.0f / 65536.0f;
+            v = f4{(float)(u.x & 0xffffu) * sc, (float)(u.x >> 16) * sc, (float)(u.y & 0xffffu) * sc,
+                   (float)(u.y >> 16) * sc};
+        }
+    } else {
+        // b_left: elements of the row from i on (<= 0 when i itself is clamped)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = ld1<DT>(X, q < b_left ? i + q : 0);
+    }
+    return v;
+}
+
 template <int DT> __device__ __forceinline__ const void* advance(const void* x, size_t elems)
 {
     return (const char*)x + elems * (DT == DT_F32 ? 4 : 2);

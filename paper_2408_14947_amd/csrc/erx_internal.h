@@ -8,7 +8,7 @@
 namespace erx {
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_U16 = 2 };
-enum { FLAG_NEED_FP64 = 1, FLAG_FP64_DONE = 2, FLAG_NOTPD = 4 };
+enum { FLAG_NEED_FP64 = 1, FLAG_FP64_DONE = 2, FLAG_NOTPD = 4, FLAG_SCORE32 = 8 };
 
 constexpr int MAX_NT = 19;   // 16-band tiles: up to 304 bands
 constexpr int SCORE_PT = 2;  // 16-pixel tiles per wave in the score kernel
@@ -47,6 +47,8 @@ struct Pass {
     int seg;               // lines per scan segment
     int pmax;              // largest pixel count (sizes the score grid)
     int vec4;              // every stream of the pass has a band count divisible by 4
+    float* mscale;         // per pass line: max |L^{-1}| (written by the factorisation when
+                           // non-null, read by the split-FP16 score kernel)
 };
 
 hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s);
@@ -58,7 +60,13 @@ hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double*
 hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,
                        float* Mt, float* mu32, int* flags, float* cond, double thr, int want_cond,
                        unsigned long long* ctr, hipStream_t s);
-hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s);
+// FP32 scores of every line, or (only != null) of the lines flagged FLAG_SCORE32 in only[]
+hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s,
+                        const int* only = nullptr);
+// the same scores on FP16 matrix cores with split operands (needs P.mscale); lines it
+// cannot represent are flagged FLAG_SCORE32 in flags[] for the FP32 kernel
+hipError_t launch_score16(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, int* flags,
+                          hipStream_t s);
 hipError_t launch_normalise(const Pass& P, hipStream_t s);
 // surrogate projection z - zref = W (x - xref) for npx FP32 pixels of b bands (W: FP16 [16][b])
 hipError_t launch_sproj(const float* X, long long npx, int b, const __half* W16, const float* xref, float* Z,

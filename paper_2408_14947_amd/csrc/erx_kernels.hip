@@ -44,39 +44,6 @@ template <> struct LP<ERX_GRAM_FP16> {
     }
 };
 
-// Four consecutive elements [i, i+4) of a line as FP32, with no branches.  With
-// VEC (b % 4 == 0 and i % 4 == 0) one 8- or 16-byte load; otherwise element
-// loads, where the caller passes ok[q] = false for elements that do not exist:
-// their offset is clamped to 0 (in bounds) and the caller ignores the value.
-// A load under a divergent branch, or a use right after it, makes the compiler
-// wait for every load in flight, so callers mask the values where they use
-// them, not here.
-template <int DT, bool VEC>
-__device__ __forceinline__ f4 ldq(const void* X, size_t i, int b_left)
-{
-    f4 v;
-    if (VEC) {
-        if (DT == DT_F32) {
-            v = *(const GLB f4*)glb((const float*)X + i);
-        } else if (DT == DT_F16) {
-            const u2v uv = *(const GLB u2v*)glb((const __half*)X + i);
-            const uint2 u = make_uint2(uv.x, uv.y);
-            const float2 a = __half22float2(*(const __half2*)&u.x), c = __half22float2(*(const __half2*)&u.y);
-            v = f4{a.x, a.y, c.x, c.y};
-        } else {
-            const u2v u = *(const GLB u2v*)glb((const uint16_t*)X + i);
-            const float sc = 1.0f / 65536.0f;
-            v = f4{(float)(u.x & 0xffffu) * sc, (float)(u.x >> 16) * sc, (float)(u.y & 0xffffu) * sc,
-                   (float)(u.y >> 16) * sc};
-        }
-    } else {
-        // b_left: elements of the row from i on (<= 0 when i itself is clamped)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = ld1<DT>(X, q < b_left ? i + q : 0);
-    }
-    return v;
-}
-
 // ============================================================================
 // Gram: per line, mean and centred covariance (Sec. III-C, Eqs. (18)-(19)).
 //
@@ -686,6 +653,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     __shared__ __attribute__((aligned(32))) T mrow_s[NT * 256];
     __shared__ __attribute__((aligned(16))) CholLds<NT> aux;
     __shared__ int fail_s;
+    __shared__ unsigned mmax_s;
 
     const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63,
               g = lane >> 4, c = lane & 15;
@@ -693,7 +661,10 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     const int gseg = sdl.seg0 + lloc / seg, l0 = (lloc / seg) * seg;
     double D = 1.0;
     for (int l = l0; l <= lloc; ++l) D *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
-    if (tid == 0) fail_s = 0;
+    if (tid == 0) {
+        fail_s = 0;
+        mmax_s = 0u;
+    }
 
     // ---- load A_IJ^T = (K_loc + D carry)_{JI} (+ eps on the diagonal)
     V A[SLOTS];
@@ -868,6 +839,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     {
         float* dstl = Mt + (size_t)line * NTL * 256;
         const bool nanout = FB && fail;
+        float mloc = 0.f;  // max |M| of this thread's entries (NaN entries are skipped by fmaxf)
 #pragma unroll
         for (int j = 0; j < SLOTS; ++j) {
             if (tI[j] < 0) continue;
@@ -875,8 +847,18 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int off = 64 * (c >> 2) + 4 * rowof<T>(g, i) + (c & 3);
-                dstl[(size_t)s * 256 + off] = nanout ? __builtin_nanf("") : (float)A[j][i];
+                const float v = (float)A[j][i];
+                dstl[(size_t)s * 256 + off] = nanout ? __builtin_nanf("") : v;
+                mloc = fmaxf(mloc, fabsf(v));
             }
+        }
+        // max |M| of the line for the split-FP16 score (wave, then workgroup)
+        if (P.mscale) {  // uniform
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, o));
+            if (lane == 0) atomicMax(&mmax_s, __float_as_uint(mloc));
+            __syncthreads();
+            if (tid == 0) glb(P.mscale)[line] = __uint_as_float(mmax_s);
         }
     }
 
@@ -1068,7 +1050,8 @@ template <int NT, int DT, bool VEC>
 // registers spill and the extra wave still wins (1.92 -> 1.86 ms at 224 bands);
 // above 14 tiles the spills grow, so two
 __global__ __launch_bounds__(256, NT <= 14 ? 3 : 2) void k_score(const Pass P, const float* __restrict__ Mt,
-                                               const float* __restrict__ mu32, int ngrp)
+                                               const float* __restrict__ mu32, const int* __restrict__ only,
+                                               int ngrp)
 {
     constexpr int NTL = NT * (NT + 1) / 2;
     constexpr int PT = SCORE_PT;
@@ -1080,6 +1063,8 @@ __global__ __launch_bounds__(256, NT <= 14 ? 3 : 2) void k_score(const Pass P, c
     const int lx = j / ngrp, grp = j - lx * ngrp;
     const int line = lx * 8 + xcd;
     if (line >= P.nlines) return;  // uniform for the workgroup
+    // the re-scoring pass of lines the split-FP16 kernel could not represent
+    if (only && !(glb(only)[line] & FLAG_SCORE32)) return;
     const StreamDesc d = stream_of_line(P, line);
     const int p = d.p, b = d.b;
     const int tid = threadIdx.x;
@@ -1332,30 +1317,31 @@ hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double*
 }
 
 template <int NT, int DT>
-static void score_one(const Pass& P, const float* Mt, const float* mu32, hipStream_t s)
+static void score_one(const Pass& P, const float* Mt, const float* mu32, const int* only, hipStream_t s)
 {
     const int per = 4 * SCORE_PT * 16;
     const int ngrp = (P.pmax + per - 1) / per;
     const dim3 grid((unsigned)((long long)(P.nlines + 7) / 8 * 8 * ngrp));
-    if (P.vec4) hipLaunchKernelGGL((k_score<NT, DT, true>), grid, dim3(256), 0, s, P, Mt, mu32, ngrp);
-    else hipLaunchKernelGGL((k_score<NT, DT, false>), grid, dim3(256), 0, s, P, Mt, mu32, ngrp);
+    if (P.vec4) hipLaunchKernelGGL((k_score<NT, DT, true>), grid, dim3(256), 0, s, P, Mt, mu32, only, ngrp);
+    else hipLaunchKernelGGL((k_score<NT, DT, false>), grid, dim3(256), 0, s, P, Mt, mu32, only, ngrp);
 }
 
 template <int DT, int... NTs>
 static void score_dispatch(std::integer_sequence<int, NTs...>, int NT, const Pass& P, const float* Mt,
-                           const float* mu32, hipStream_t s)
+                           const float* mu32, const int* only, hipStream_t s)
 {
-    ((NT == NTs + 1 ? score_one<NTs + 1, DT>(P, Mt, mu32, s) : void()), ...);
+    ((NT == NTs + 1 ? score_one<NTs + 1, DT>(P, Mt, mu32, only, s) : void()), ...);
 }
 
-hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s)
+hipError_t launch_score(int dtype, const Pass& P, int NT, const float* Mt, const float* mu32, hipStream_t s,
+                        const int* only)
 {
     if (NT < 1 || NT > MAX_NT) return hipErrorInvalidValue;
     auto seq = std::make_integer_sequence<int, MAX_NT>();
     switch (dtype) {
-    case DT_F32: score_dispatch<DT_F32>(seq, NT, P, Mt, mu32, s); break;
-    case DT_F16: score_dispatch<DT_F16>(seq, NT, P, Mt, mu32, s); break;
-    default: score_dispatch<DT_U16>(seq, NT, P, Mt, mu32, s); break;
+    case DT_F32: score_dispatch<DT_F32>(seq, NT, P, Mt, mu32, only, s); break;
+    case DT_F16: score_dispatch<DT_F16>(seq, NT, P, Mt, mu32, only, s); break;
+    default: score_dispatch<DT_U16>(seq, NT, P, Mt, mu32, only, s); break;
     }
     return hipGetLastError();
 }

@@ -45,7 +45,7 @@ size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Byte offsets of the buffers of one pass of C lines inside the scratch.
 struct Layout {
-    size_t stats, carry, Mt, mu32, flags, cond, ctr, end;
+    size_t stats, carry, Mt, mu32, mscale, flags, cond, ctr, end;
 };
 
 Layout layout(int C, int seg, long long E, int NTL, int bpad)
@@ -56,7 +56,8 @@ Layout layout(int C, int seg, long long E, int NTL, int bpad)
     L.carry = up256(L.stats + (size_t)C * E * sizeof(double));
     L.Mt = up256(L.carry + nseg * E * sizeof(double));
     L.mu32 = up256(L.Mt + (size_t)C * NTL * 256 * sizeof(float));
-    L.flags = up256(L.mu32 + (size_t)C * bpad * sizeof(float));
+    L.mscale = up256(L.mu32 + (size_t)C * bpad * sizeof(float));
+    L.flags = up256(L.mscale + (size_t)C * sizeof(float));
     L.cond = up256(L.flags + (size_t)C * sizeof(int));
     L.ctr = up256(L.cond + (size_t)C * sizeof(float));
     L.end = up256(L.ctr + 4 * sizeof(unsigned long long));
@@ -104,6 +105,8 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
         return set_error(ERX_EINVAL, "unknown precision %d", c.precision);
     if (!(c.fp64_cond_threshold >= 0.0)) return set_error(ERX_EINVAL, "fp64_cond_threshold must be >= 0");
     if (c.cond_estimate < -1 || c.cond_estimate > 1) return set_error(ERX_EINVAL, "cond_estimate must be -1, 0 or 1");
+    if (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32)
+        return set_error(ERX_EINVAL, "unknown score_arith %d", c.score_arith);
     if (c.normalise != 0) return set_error(ERX_EINVAL, "erx_push_lines_noalloc does not normalise (normalise must be 0)");
     if (c.block_lines < 1 || c.scan_lines < 1) return set_error(ERX_EINVAL, "block_lines and scan_lines must be >= 1");
     if (n < 1) return set_error(ERX_EINVAL, "n must be >= 1, got %d", n);
@@ -149,6 +152,7 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
     double* carry = (double*)(base + L.carry);
     float* Mt = (float*)(base + L.Mt);
     float* mu32 = (float*)(base + L.mu32);
+    float* mscale = (float*)(base + L.mscale);
     int* flags = (int*)(base + L.flags);
     float* cond = (float*)(base + L.cond);
     unsigned long long* ctr = (unsigned long long*)(base + L.ctr);  // counters, not reported here
@@ -187,7 +191,8 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
         P.seg = seg;
         P.pmax = c.pixels;
         P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)src % (4 * esz)) == 0;
-        e = run_pass(s, P, NT, c.dtype, c.precision, stats, carry, Mt, mu32, flags, cond, thr, want_cond, fp64_pass,
+        P.mscale = mscale;
+        e = run_pass(s, P, NT, c.dtype, c.precision, c.score_arith, stats, carry, Mt, mu32, flags, cond, thr, want_cond, fp64_pass,
                      false, ctr, nullptr);
         if (e != hipSuccess) return set_error(ERX_EDEVICE, "launch failed: %s", hipGetErrorString(e));
         t += nc;

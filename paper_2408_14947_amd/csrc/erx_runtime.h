@@ -11,7 +11,7 @@
 
 namespace erx {
 
-enum { K_GRAM, K_SCAN_LOCAL, K_SCAN_CARRY, K_CHOL32, K_CHOL64, K_SCORE, K_NORMALISE, K_COUNT };
+enum { K_GRAM, K_SCAN_LOCAL, K_SCAN_CARRY, K_CHOL32, K_CHOL64, K_SCORE, K_SCORE_REDO, K_NORMALISE, K_COUNT };
 
 // Brackets launches with HIP events on the launch stream and sums their
 // durations per kernel kind.
@@ -40,8 +40,11 @@ struct Profiler {
 
 // Launch the whole hot path for one pass: per-line mean and Gram, segment
 // scan, carries, factorisation (FP32 with FP64 re-factor when thr > 0,
-// FP64 for every line when thr == 0), scores, optional normalisation.
-hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, double* stats, double* carry, float* Mt,
+// FP64 for every line when thr == 0), scores (split FP16 with an FP32 pass
+// over the lines it flags, or FP32; the split kernel needs P.mscale),
+// optional normalisation.
+hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, int sarith, double* stats,
+                    double* carry, float* Mt,
                     float* mu32, int* flags, float* cond, double thr, int want_cond, bool fp64_pass,
                     bool normalise, unsigned long long* ctr, Profiler* prof);
 

@@ -9,7 +9,7 @@ namespace erx {
 namespace {
 thread_local std::string g_err = "no error";
 const char* kKernelNames[K_COUNT] = {"gram", "scan_local", "scan_carry", "chol_fp32", "chol_fp64", "score",
-                                     "normalise"};
+                                     "score_fp32_redo", "normalise"};
 }  // namespace
 
 int set_error(int code, const char* fmt, ...)
@@ -72,7 +72,8 @@ void Profiler::release()
     pool.clear();
 }
 
-hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, double* stats, double* carry, float* Mt,
+hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, int sarith, double* stats,
+                    double* carry, float* Mt,
                     float* mu32, int* flags, float* cond, double thr, int want_cond, bool fp64_pass,
                     bool normalise, unsigned long long* ctr, Profiler* prof)
 {
@@ -99,7 +100,15 @@ hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, d
         });
         if (e != hipSuccess) return e;
     }
-    if ((e = T(K_SCORE, [&] { return launch_score(dtype, P, NT, Mt, mu32, s); })) != hipSuccess) return e;
+    if (sarith == ERX_SCORE_SPLIT16 && P.mscale) {
+        if ((e = T(K_SCORE, [&] { return launch_score16(dtype, P, NT, Mt, mu32, flags, s); })) != hipSuccess)
+            return e;
+        // lines the split kernel flagged (each workgroup of the others returns at once)
+        if ((e = T(K_SCORE_REDO, [&] { return launch_score(dtype, P, NT, Mt, mu32, s, flags); })) != hipSuccess)
+            return e;
+    } else {
+        if ((e = T(K_SCORE, [&] { return launch_score(dtype, P, NT, Mt, mu32, s); })) != hipSuccess) return e;
+    }
     if (normalise)
         if ((e = T(K_NORMALISE, [&] { return launch_normalise(P, s); })) != hipSuccess) return e;
     return hipSuccess;

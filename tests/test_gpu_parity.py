@@ -308,6 +308,43 @@ def test_not_positive_definite_fp32_only(erx):
     assert e.value.code == erx.ERX_ENOTPD
 
 
+@pytest.mark.parametrize("b,p,T", [(16, 100, 40), (108, 640, 60), (224, 256, 40), (300, 130, 20)])
+def test_parity_fp32_score_arith(erx, b, p, T):
+    """The FP32 matrix-core score (score_arith = fp32) against the oracle, and the
+    default split-FP16 score against it, on the same lines."""
+    log(f"FP32 and split-FP16 score arithmetic b={b} p={p} T={T}")
+    scene = datagen.make_scene(25, b, b, p, T)
+    X, _ = datagen.lines(scene, 0, T)
+    want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
+    got32, _ = run_gpu(erx, X, score_arith="fp32")
+    got16, det = run_gpu(erx, X)
+    e32, e16 = rel_err(got32, want).max(), rel_err(got16, want).max()
+    _, flags = det.line_info()
+    log(f"  max err fp32 {e32:.3e}  split16 {e16:.3e}  re-scored lines {int(((flags & erx.FLAG_SCORE32) > 0).sum())}")
+    assert e32 <= TOL and e16 <= TOL
+
+
+def test_split_score_falls_back_to_fp32(erx):
+    """A pixel whose residuals over its first 16 bands are tiny (that block equals the
+    line mean, momentum 1) and large elsewhere cannot be held by the split-FP16 scale
+    chosen from its first column: its line is flagged and scored again in FP32, and
+    every score still matches the oracle."""
+    log("split-FP16 score: FP32 re-score of flagged lines")
+    rng = np.random.default_rng(26)
+    T, p, b = 6, 96, 40
+    X = (0.5 + 0.05 * rng.standard_normal((T, p, b))).astype(np.float32)
+    for t in (1, 4):  # lines 1 and 4: pixel 7's first 16 bands sit on the line mean
+        X[t, 7, :16] = X[t, np.arange(p) != 7, :16].astype(np.float64).mean(0)
+        X[t, 7, 3] += np.float32(2e-6)  # a residual of about 2e-6 against about 0.05 in later bands
+    got, det = run_gpu(erx, torch.from_numpy(X), momentum=1.0)
+    want = oracle.run(X, 1.0, 1e-5)["delta"]
+    _, flags = det.line_info()
+    redo = (flags & erx.FLAG_SCORE32) > 0
+    log(f"  flagged lines {np.nonzero(redo)[0].tolist()}  max err {rel_err(got, want).max():.3e}")
+    assert redo[1] and redo[4]
+    assert rel_err(got, want).max() <= TOL
+
+
 def test_minimal_c_abi_create_push_scores(erx):
     """The three calls of the minimal boundary, exactly: erx_create(bands, pixels,
     momentum) -> erx_push_lines(handle, lines, n) with FP32 lines in HOST memory ->
