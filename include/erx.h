@@ -98,7 +98,14 @@ typedef struct erx_config {
     int cond_estimate; /* 1-norm condition estimate per line: -1 (default) only when it decides
                           the FP64 re-factor (0 < threshold < inf), 0 never, 1 always */
     int score_arith;   /* ERX_SCORE_SPLIT16 (default) or ERX_SCORE_FP32 */
+    int srp_dims;      /* 0 (default): every band is kept.  d in [1, ERX_SRP_MAX_DIMS]: each line is
+                          first projected to d dimensions with the sparse random projection of
+                          Sec. III-B (the paper's default is 5) and the detector runs on the
+                          projected lines: state, statistics and scores are those of Z_t = X_t W */
+    unsigned long long srp_seed; /* seed of the projection weights (erx_srp_matrix) */
 } erx_config;
+
+#define ERX_SRP_MAX_DIMS 32
 
 #define ERX_MAX_BANDS 304
 
@@ -106,6 +113,16 @@ typedef struct erx_config {
  * threshold 0 (FP64 factorisation), no normalisation, block_lines 2048,
  * scan_lines 64, cond_estimate -1, split-FP16 score. */
 ERX_API void erx_config_default(erx_config *cfg, int bands, int pixels, float momentum);
+
+/* The sparse random projection W in R^{bands x dims} of Sec. III-B, as a detector with
+ * srp_dims = dims and srp_seed = seed uses it: w_ij = sqrt(s/dims) * (+1 with probability
+ * 1/(2s), 0 with 1 - 1/s, -1 with 1/(2s)), s = sqrt(bands), so about dims * sqrt(bands)
+ * weights are non-zero.  The draws are SplitMix64 outputs (the published generator, as a
+ * counter): weight (i, j) takes output k = i * dims + j + 1 from state seed, as the
+ * uniform (u >> 11) * 2^-53.  W: host buffer [bands][dims], row-major.  Host only (no
+ * device work); ERX_EINVAL for bands outside [1, ERX_MAX_BANDS] or dims outside
+ * [1, ERX_SRP_MAX_DIMS]. */
+ERX_API int erx_srp_matrix(int bands, int dims, unsigned long long seed, float *W);
 
 /* Create a detector on the current HIP device.  Returns NULL on error
  * (erx_last_error says why).  erx_create uses the defaults above. */
@@ -138,7 +155,8 @@ ERX_API int erx_scores_normalised(erx_ctx *h, float *out);
 ERX_API int erx_labels(erx_ctx *h, float tau, unsigned char *out);
 
 /* Detector state: number of lines absorbed, background mean [b] and full
- * symmetric covariance [b*b] (FP64, host buffers).  erx_set_state with t = 0
+ * symmetric covariance [b*b] (FP64, host buffers), with b = srp_dims for a detector
+ * that projects its lines (Sec. III-B).  erx_set_state with t = 0
  * resets the detector; the next line initialises the background. */
 ERX_API int erx_get_state(erx_ctx *h, long long *t, double *mu, double *K);
 ERX_API int erx_set_state(erx_ctx *h, long long t, const double *mu, const double *K);
@@ -333,6 +351,29 @@ ERX_API void erx_surrogate_detector_destroy(erx_sdet *sd);
 #define ERX_NOALLOC_SCRATCH_BYTES (48u << 20)
 ERX_API int erx_push_lines_noalloc(const erx_config *cfg, double *state, long long t0, const void *lines, int n,
                                    float *out, void *hip_stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Detection metrics of Sec. IV-C for scored pixels with ground truth.  TPR(tau) and
+ * FPR(tau) are the fractions of anomalies and of background pixels scoring >= tau
+ * (Eqs. (26)-(27)); the ROC curve visits every distinct score as a threshold and auc is
+ * its area (the fraction of (anomaly, background) pairs ranked correctly, ties counting
+ * one half).  auc_tpr_tau and auc_fpr_tau are the areas under TPR(tau) and FPR(tau) for
+ * tau in [0, 1] with the scores min-max normalised over the evaluated pixels (0 when all
+ * are equal); auc_td = (auc + auc_tpr_tau) / 2 and auc_bs = (auc - auc_fpr_tau + 1) / 2
+ * (Eqs. (28)-(29)).  Pixels whose score is not finite are left out and counted.
+ * --------------------------------------------------------------------------------------- */
+typedef struct erx_detection_metrics_t {
+    double auc, auc_tpr_tau, auc_fpr_tau, auc_td, auc_bs;
+    long long positives;  /* anomalies evaluated */
+    long long negatives;  /* background pixels evaluated */
+    long long excluded;   /* pixels with a non-finite score */
+} erx_detection_metrics_t;
+/* scores: device FP32 [n]; truth: device bytes [n], non-zero = anomaly; n >= 2.  Runs on
+ * hip_stream (NULL: the default stream), allocates a sort buffer of the smaller class for
+ * the call and blocks until the result is in *out.  ERX_EINVAL for host buffers, or when
+ * no anomaly or no background pixel has a finite score; ERX_EDEVICE on device failures. */
+ERX_API int erx_detection_metrics(const float *scores, const unsigned char *truth, long long n, void *hip_stream,
+                                  erx_detection_metrics_t *out);
 
 /* Wait for all work enqueued on the handle's stream. */
 ERX_API int erx_synchronize(erx_ctx *h);

@@ -40,13 +40,15 @@ def roc_curve(scores, truth):
     """(FPR, TPR, thresholds): one point per distinct score (descending), plus (0, 0)."""
     s, y, _ = _split(scores, truth)
     P, N = int(y.sum()), int((~y).sum())
-    thr = np.unique(s)[::-1]
-    fpr, tpr = [0.0], [0.0]
-    for t in thr:
-        ge = s >= t
-        tpr.append(float((ge & y).sum()) / P)
-        fpr.append(float((ge & ~y).sum()) / N)
-    return np.array(fpr), np.array(tpr), thr
+    thr, inv = np.unique(s, return_inverse=True)      # ascending distinct scores
+    pos_at = np.bincount(inv, weights=y, minlength=thr.size)
+    neg_at = np.bincount(inv, weights=~y, minlength=thr.size)
+    # pixels with score >= thr[i]: counts from the top threshold down
+    tp = np.cumsum(pos_at[::-1])
+    fp = np.cumsum(neg_at[::-1])
+    tpr = np.concatenate([[0.0], tp / P])
+    fpr = np.concatenate([[0.0], fp / N])
+    return fpr, tpr, thr[::-1]
 
 
 def auc(scores, truth) -> float:
@@ -66,15 +68,12 @@ def rate_tau_area(scores, truth, positive: bool) -> float:
     consecutive distinct normalised scores, where it equals #(class >= v_i) / #class."""
     s, y, _ = _split(scores, truth)
     v = _normalised(s)
-    cls = v[y] if positive else v[~y]
+    cls = np.sort(v[y] if positive else v[~y])
     steps = np.unique(v)
-    area, prev = 0.0, 0.0
-    for t in steps:
-        if t <= 0.0:
-            continue
-        area += (t - prev) * float((cls >= t).sum()) / cls.size
-        prev = t
-    return area
+    steps = steps[steps > 0.0]
+    prev = np.concatenate([[0.0], steps[:-1]])
+    at_least = cls.size - np.searchsorted(cls, steps, side="left")  # #(class >= v_i)
+    return float(np.sum((steps - prev) * at_least / cls.size))
 
 
 def detection_metrics(scores, truth) -> dict:

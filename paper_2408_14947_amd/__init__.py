@@ -36,6 +36,7 @@ EXPORTS = (
     "erx_surrogate_grads", "erx_surrogate_destroy", "erx_surrogate_detector_create",
     "erx_surrogate_detector_push", "erx_surrogate_detector_scores", "erx_surrogate_detector_status",
     "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup", "erx_push_lines_noalloc",
+    "erx_detection_metrics", "erx_srp_matrix",
 )
 SURR_K, SURR_HIDDEN = 16, 64
 
@@ -51,7 +52,14 @@ class Config(C.Structure):
                 ("ridge", C.c_float), ("warmup", C.c_int), ("dtype", C.c_int),
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
-                ("cond_estimate", C.c_int), ("score_arith", C.c_int)]
+                ("cond_estimate", C.c_int), ("score_arith", C.c_int), ("srp_dims", C.c_int),
+                ("srp_seed", C.c_ulonglong)]
+
+
+class DetectionMetrics(C.Structure):
+    _fields_ = [("auc", C.c_double), ("auc_tpr_tau", C.c_double), ("auc_fpr_tau", C.c_double),
+                ("auc_td", C.c_double), ("auc_bs", C.c_double), ("positives", C.c_longlong),
+                ("negatives", C.c_longlong), ("excluded", C.c_longlong)]
 
 
 class TuneResult(C.Structure):
@@ -127,6 +135,8 @@ def load(path: str = LIB_PATH):
         "erx_autotune": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
         "erx_tune_lookup": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
         "erx_push_lines_noalloc": (ip, [C.POINTER(Config), vp, C.c_longlong, vp, ip, vp, vp]),
+        "erx_detection_metrics": (ip, [vp, vp, C.c_longlong, vp, C.POINTER(DetectionMetrics)]),
+        "erx_srp_matrix": (ip, [ip, ip, C.c_ulonglong, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -176,9 +186,10 @@ class Detector:
                  dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
                  scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
-                 score_arith: str = "split16"):
+                 score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
-        stream, None = a stream owned by the handle."""
+        stream, None = a stream owned by the handle.  srp_dims > 0: project every line
+        to that many dimensions first (Sec. III-B, weights from srp_matrix)."""
         lib = load()
         cfg = Config()
         lib.erx_config_default(C.byref(cfg), int(bands), int(pixels), float(momentum))
@@ -192,8 +203,11 @@ class Detector:
         cfg.scan_lines = int(scan_lines)
         cfg.cond_estimate = int(cond_estimate)
         cfg.score_arith = SCORE_ARITH[score_arith]
+        cfg.srp_dims = int(srp_dims)
+        cfg.srp_seed = int(srp_seed)
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
+        self.work_bands = int(srp_dims) if srp_dims else int(bands)
         self._lib = lib
         self._h = lib.erx_create_ex(C.byref(cfg))
         if not self._h:
@@ -269,8 +283,8 @@ class Detector:
     # -- state and diagnostics
     def state(self):
         t = C.c_longlong(0)
-        mu = np.empty(self.bands)
-        K = np.empty((self.bands, self.bands))
+        mu = np.empty(self.work_bands)
+        K = np.empty((self.work_bands, self.work_bands))
         _check(self._lib.erx_get_state(self._h, C.byref(t), C.c_void_p(mu.ctypes.data),
                                        C.c_void_p(K.ctypes.data)))
         return int(t.value), mu, K
@@ -444,7 +458,33 @@ def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge:
     return int(t0) + n
 
 
-__all__ = ["Detector", "Batch", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
+def srp_matrix(bands: int, dims: int, seed: int) -> np.ndarray:
+    """erx_srp_matrix: the projection weights W [bands][dims] a detector with srp_dims =
+    dims and srp_seed = seed uses (host computation, no GPU needed)."""
+    W = np.empty((int(bands), int(dims)), np.float32)
+    _check(load().erx_srp_matrix(int(bands), int(dims), C.c_ulonglong(int(seed)), C.c_void_p(W.ctypes.data)))
+    return W
+
+
+def detection_metrics(scores, truth, stream: Optional[int] = -1) -> dict:
+    """erx_detection_metrics on device tensors: scores (float32) and truth (uint8 / bool,
+    non-zero = anomaly) of the same number of pixels."""
+    lib = load()
+    n = int(scores.numel())
+    if int(truth.numel()) != n:
+        raise ValueError("scores and truth need the same number of elements")
+    if truth.dtype != __import__("torch").uint8:
+        truth = truth.to(__import__("torch").uint8)
+    truth = truth.contiguous()
+    if stream == -1:
+        stream = _torch_stream()
+    m = DetectionMetrics()
+    _check(lib.erx_detection_metrics(C.c_void_p(_ptr(scores.contiguous())), C.c_void_p(_ptr(truth)), n,
+                                     C.c_void_p(stream), C.byref(m)))
+    return {k: getattr(m, k) for k, _ in DetectionMetrics._fields_}
+
+
+__all__ = ["Detector", "Batch", "detection_metrics", "srp_matrix", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
            "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "FLAG_SCORE32", "MAX_BANDS", "SCORE_ARITH", "push_lines_noalloc",
            "noalloc_state_entries", "NOALLOC_SCRATCH_BYTES"]
 

@@ -32,6 +32,7 @@ size_t elem_size(int dtype) { return dtype == ERX_F32 ? 4 : 2; }
 
 struct erx_ctx {
     erx_config cfg;
+    int wb = 0;  // bands the detector works in: srp_dims when the projection is on, else bands
     int NT = 0, NTL = 0, bpad = 0;
     long long E = 0;
     int device = 0;
@@ -52,6 +53,14 @@ struct erx_ctx {
     float* scores_n = nullptr; // [cap][p]
     unsigned char* labels = nullptr;  // [cap][p]
     void* staging = nullptr;   // [C][p][b] host-input staging
+    float* srpW = nullptr;     // [b][d] projection weights (srp_dims > 0)
+    float* zbuf = nullptr;     // [C][p][d] projected lines of one pass
+    // the projection is taken relative to a reference pixel, z - W^T x_ref = W^T (x - x_ref):
+    // the scores do not change (a common shift of all pixels) and the FP32 projection keeps
+    // the residuals' digits; the reference is the first pixel the detector sees
+    float* srp_xref = nullptr; // [b] FP32 reference pixel (device)
+    std::vector<float> srpW_h; // [b][d] host copy of W
+    bool srp_ref_set = false;
     long long cap = 0;
     int last_n = 0;
     long long last_t0 = 0;
@@ -66,7 +75,7 @@ namespace {
 void free_all(erx_ctx* h)
 {
     void* ptrs[] = {h->state, h->stats, h->carry, h->Mt, h->mu32, h->mscale, h->ctr, h->flags, h->cond,
-                    h->scores, h->scores_n, h->labels, h->staging};
+                    h->scores, h->scores_n, h->labels, h->staging, h->srpW, h->zbuf, h->srp_xref};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     h->prof.release();
@@ -118,6 +127,22 @@ long long packed_offset(int r, int c, int NT)
     const int I = r >> 4, J = c >> 4, rr = r & 15, cc = c & 15;
     const long long u = (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);
     return u * 256 + (16 * (rr >> 2) + cc) * 4 + (rr & 3);
+}
+
+// W^T x_ref in FP64 (zeros without a projection): the state holds the background
+// of z - W^T x_ref
+hipError_t srp_zref(erx_ctx* h, std::vector<double>& zref)
+{
+    zref.assign(h->wb, 0.0);
+    if (!h->srpW) return hipSuccess;
+    const int b = h->cfg.bands, d = h->wb;
+    std::vector<float> xr(b);
+    hipError_t e = hipMemcpyAsync(xr.data(), h->srp_xref, b * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < b; ++i)
+        for (int j = 0; j < d; ++j) zref[j] += (double)h->srpW_h[(size_t)i * d + j] * (double)xr[i];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -188,6 +213,10 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "unknown score_arith %d", c.score_arith);
         return nullptr;
     }
+    if (c.srp_dims < 0 || c.srp_dims > ERX_SRP_MAX_DIMS) {
+        fail(ERX_EINVAL, "srp_dims must be 0 (off) or in [1, %d], got %d", ERX_SRP_MAX_DIMS, c.srp_dims);
+        return nullptr;
+    }
     if (c.block_lines < 1 || c.scan_lines < 1 || c.warmup < 0 || (c.normalise != 0 && c.normalise != 1)) {
         fail(ERX_EINVAL, "block_lines and scan_lines must be >= 1, warmup >= 0, normalise 0/1");
         return nullptr;
@@ -198,7 +227,8 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         return nullptr;
     }
     h->cfg = c;
-    h->NT = (c.bands + 15) / 16;
+    h->wb = c.srp_dims > 0 ? c.srp_dims : c.bands;
+    h->NT = (h->wb + 15) / 16;
     h->NTL = h->NT * (h->NT + 1) / 2;
     h->bpad = 16 * h->NT;
     h->E = stat_entries(h->NT);
@@ -213,6 +243,16 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
          dmalloc(&h->mu32, C * h->bpad * sizeof(float)) == hipSuccess &&
          dmalloc(&h->mscale, C * sizeof(float)) == hipSuccess &&
          dmalloc(&h->ctr, 4 * sizeof(unsigned long long)) == hipSuccess;
+    if (ok && c.srp_dims > 0) {
+        std::vector<float>& W = h->srpW_h;
+        W.resize((size_t)c.bands * c.srp_dims);
+        ok = erx_srp_matrix(c.bands, c.srp_dims, c.srp_seed, W.data()) == ERX_OK &&
+             dmalloc(&h->srpW, W.size() * sizeof(float)) == hipSuccess &&
+             dmalloc(&h->srp_xref, (size_t)c.bands * sizeof(float)) == hipSuccess &&
+             hipMemset(h->srp_xref, 0, (size_t)c.bands * sizeof(float)) == hipSuccess &&
+             hipMemcpy(h->srpW, W.data(), W.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+             dmalloc(&h->zbuf, C * (size_t)c.pixels * c.srp_dims * sizeof(float)) == hipSuccess;
+    }
     ok = ok && hipMemset(h->state, 0, h->E * sizeof(double)) == hipSuccess &&
          hipMemset(h->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
     if (!ok) {
@@ -274,6 +314,18 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
                                   hipMemcpyHostToDevice, h->stream));
             src = h->staging;
         }
+        // the sparse random projection (Sec. III-B) turns the pass into one over Z = X W in FP32
+        int pdt = c.dtype;
+        if (h->srpW) {
+            if (!h->srp_ref_set) {  // the first pixel the detector sees becomes the reference
+                HIPCHK(launch_srp_ref(c.dtype, src, c.bands, h->srp_xref, h->stream));
+                h->srp_ref_set = true;
+            }
+            HIPCHK(launch_srp_project(c.dtype, src, (long long)nc * c.pixels, c.bands, h->srpW, h->srp_xref, h->wb,
+                                      h->zbuf, h->stream));
+            src = h->zbuf;
+            pdt = ERX_F32;
+        }
         Pass P{};
         P.sd = nullptr;
         P.one.x = src;
@@ -284,7 +336,7 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.one.alpha = c.momentum;
         P.one.eps = c.ridge;
         P.one.p = c.pixels;
-        P.one.b = c.bands;
+        P.one.b = h->wb;
         P.one.n = nc;
         P.one.line0 = 0;
         P.one.seg0 = 0;
@@ -294,9 +346,9 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.seg = seg;
         P.pmax = c.pixels;
         // 4-band vector loads need b % 4 == 0 and a 4-element aligned buffer
-        P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)src % (4 * esz)) == 0;
+        P.vec4 = (h->wb % 4) == 0 && ((uintptr_t)src % (4 * elem_size(pdt))) == 0;
         P.mscale = h->mscale;
-        HIPCHK(run_pass(h->stream, P, h->NT, c.dtype, c.precision, c.score_arith, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
+        HIPCHK(run_pass(h->stream, P, h->NT, pdt, c.precision, c.score_arith, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));
         h->t += nc;
@@ -371,10 +423,12 @@ int erx_get_state(erx_ctx* h, long long* t, double* mu, double* K)
     std::vector<double> s(h->E);
     HIPCHK(hipMemcpyAsync(s.data(), h->state, h->E * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    const int b = h->cfg.bands, NT = h->NT;
+    const int b = h->wb, NT = h->NT;
     if (t) *t = h->t;
+    std::vector<double> zref;
+    HIPCHK(srp_zref(h, zref));
     if (mu)
-        for (int j = 0; j < b; ++j) mu[j] = s[(size_t)h->NTL * 256 + j];
+        for (int j = 0; j < b; ++j) mu[j] = s[(size_t)h->NTL * 256 + j] + zref[j];
     if (K)
         for (int r = 0; r < b; ++r)
             for (int c = 0; c < b; ++c)
@@ -388,9 +442,12 @@ int erx_set_state(erx_ctx* h, long long t, const double* mu, const double* K)
     if (t < 0) return fail(ERX_EINVAL, "t must be >= 0");
     if (t > 0 && (!mu || !K)) return fail(ERX_EINVAL, "mu and K are required when t > 0");
     std::vector<double> s(h->E, 0.0);
-    const int b = h->cfg.bands, NT = h->NT;
+    const int b = h->wb, NT = h->NT;
+    if (h->srpW && !h->srp_ref_set) h->srp_ref_set = true;  // the state fixes the reference: x_ref = 0
+    std::vector<double> zref;
+    HIPCHK(srp_zref(h, zref));
     if (t > 0) {
-        for (int j = 0; j < b; ++j) s[(size_t)h->NTL * 256 + j] = mu[j];
+        for (int j = 0; j < b; ++j) s[(size_t)h->NTL * 256 + j] = mu[j] - zref[j];
         for (int r = 0; r < b; ++r)
             for (int c = r; c < b; ++c) {
                 s[packed_offset(r, c, NT)] = K[(size_t)r * b + c];

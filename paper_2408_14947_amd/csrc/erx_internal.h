@@ -80,6 +80,11 @@ hipError_t launch_gram1x(const Pass& P, double* stats, hipStream_t s);
 // 0 selects the variant that streams every tile from global memory.
 hipError_t launch_small(int dtype, const Pass& P, int normalise, unsigned long long* ctr, int lds_line_bytes,
                         hipStream_t s);
+// sparse random projection Z = (X - 1 xref^T) W of npix pixels of b bands (W device FP32 [b][d],
+// xref FP32 [b], Z FP32 [npix][d]); launch_srp_ref stores the first pixel of X as xref
+hipError_t launch_srp_project(int dtype, const void* X, long long npix, int b, const float* W, const float* xref,
+                              int d, float* Z, hipStream_t s);
+hipError_t launch_srp_ref(int dtype, const void* X, int b, float* xref, hipStream_t s);
 hipError_t launch_labels(const float* dn, int n, int p, float tau, long long t0, int warmup,
                          unsigned char* out, hipStream_t s);
 

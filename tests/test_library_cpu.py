@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -122,3 +123,20 @@ def test_noalloc_rejects_invalid_arguments_before_device_work():
     assert lib.erx_push_lines_noalloc(C.byref(cfg), dummy, -1, dummy, 4, dummy, None) == erx.ERX_EINVAL
     assert lib.erx_push_lines_noalloc(None, dummy, 0, dummy, 4, dummy, None) == erx.ERX_EINVAL
     assert erx.noalloc_state_entries(224) == 256 * 105 + 224
+
+
+def test_srp_matrix_matches_reference_generator():
+    """erx_srp_matrix (host code of the library) draws exactly the weights of the FP64
+    reference (both implement the published SplitMix64 generator): same zero pattern
+    and signs, values equal after rounding the reference's to FP32."""
+    erx, _ = _lib()
+    from oracle import srp
+    for b, d, seed in [(108, 5, 0), (224, 5, 12345), (13, 3, 7), (300, 32, 2 ** 63 + 5)]:
+        W = erx.srp_matrix(b, d, seed)
+        ref = srp.srp_matrix(b, d, seed)
+        assert W.shape == (b, d)
+        assert np.array_equal(W, ref.astype(np.float32)), (b, d, seed)
+    with pytest.raises(erx.ErxError):
+        erx.srp_matrix(100, 33, 0)
+    with pytest.raises(erx.ErxError):
+        erx.srp_matrix(0, 5, 0)
