@@ -103,7 +103,14 @@ typedef struct erx_config {
                           Sec. III-B (the paper's default is 5) and the detector runs on the
                           projected lines: state, statistics and scores are those of Z_t = X_t W */
     unsigned long long srp_seed; /* seed of the projection weights (erx_srp_matrix) */
+    int background;    /* ERX_BG_EMA (default): the moving averages of Sec. III-C.  ERX_BG_IMC: the
+                          paper's "No EMAs" ablation (Sec. IV-D): every pixel of every line seen so
+                          far weighs equally; the background of line t is the mean and the sample
+                          covariance (divisor N - 1) of the N = t * pixels pooled pixels (the batch
+                          Welford update), plus the ridge; momentum is then unused */
 } erx_config;
+
+enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };
 
 #define ERX_SRP_MAX_DIMS 32
 

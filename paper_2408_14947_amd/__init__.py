@@ -20,6 +20,7 @@ ERX_OK, ERX_EINVAL, ERX_ENOMEM, ERX_EDEVICE, ERX_ENOTPD, ERX_ESTATE = 0, -1, -2,
 DTYPES = {"f32": 0, "f16": 1, "u16": 2}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 SCORE_ARITH = {"split16": 0, "fp32": 1}
+BACKGROUNDS = {"ema": 0, "imc": 1}
 FLAG_NEED_FP64, FLAG_FP64_DONE, FLAG_NOTPD, FLAG_SCORE32 = 1, 2, 4, 8
 MAX_BANDS = 304
 
@@ -53,7 +54,7 @@ class Config(C.Structure):
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
                 ("cond_estimate", C.c_int), ("score_arith", C.c_int), ("srp_dims", C.c_int),
-                ("srp_seed", C.c_ulonglong)]
+                ("srp_seed", C.c_ulonglong), ("background", C.c_int)]
 
 
 class DetectionMetrics(C.Structure):
@@ -186,7 +187,8 @@ class Detector:
                  dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
                  scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
-                 score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0):
+                 score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0,
+                 background: str = "ema"):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
         stream, None = a stream owned by the handle.  srp_dims > 0: project every line
         to that many dimensions first (Sec. III-B, weights from srp_matrix)."""
@@ -205,6 +207,7 @@ class Detector:
         cfg.score_arith = SCORE_ARITH[score_arith]
         cfg.srp_dims = int(srp_dims)
         cfg.srp_seed = int(srp_seed)
+        cfg.background = BACKGROUNDS[background]
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
         self.work_bands = int(srp_dims) if srp_dims else int(bands)

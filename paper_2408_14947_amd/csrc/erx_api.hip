@@ -213,6 +213,10 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "unknown score_arith %d", c.score_arith);
         return nullptr;
     }
+    if (c.background != ERX_BG_EMA && c.background != ERX_BG_IMC) {
+        fail(ERX_EINVAL, "background must be ERX_BG_EMA or ERX_BG_IMC, got %d", c.background);
+        return nullptr;
+    }
     if (c.srp_dims < 0 || c.srp_dims > ERX_SRP_MAX_DIMS) {
         fail(ERX_EINVAL, "srp_dims must be 0 (off) or in [1, %d], got %d", ERX_SRP_MAX_DIMS, c.srp_dims);
         return nullptr;
@@ -236,7 +240,8 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
     const size_t nseg = (C + c.scan_lines - 1) / c.scan_lines;
     bool ok = hipGetDevice(&h->device) == hipSuccess && hipStreamCreate(&h->own_stream) == hipSuccess;
     h->stream = h->own_stream;
-    ok = ok && dmalloc(&h->state, h->E * sizeof(double)) == hipSuccess &&
+    // the state, then (IMC) the stream's reference mean
+    ok = ok && dmalloc(&h->state, (h->E + h->bpad) * sizeof(double)) == hipSuccess &&
          dmalloc(&h->stats, C * h->E * sizeof(double)) == hipSuccess &&
          dmalloc(&h->carry, nseg * h->E * sizeof(double)) == hipSuccess &&
          dmalloc(&h->Mt, C * h->NTL * 256 * sizeof(float)) == hipSuccess &&
@@ -253,7 +258,7 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
              hipMemcpy(h->srpW, W.data(), W.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
              dmalloc(&h->zbuf, C * (size_t)c.pixels * c.srp_dims * sizeof(float)) == hipSuccess;
     }
-    ok = ok && hipMemset(h->state, 0, h->E * sizeof(double)) == hipSuccess &&
+    ok = ok && hipMemset(h->state, 0, (h->E + h->bpad) * sizeof(double)) == hipSuccess &&
          hipMemset(h->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
     if (!ok) {
         const hipError_t e = hipGetLastError();
@@ -334,6 +339,7 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.one.state = h->state;
         P.one.t0 = h->t;
         P.one.alpha = c.momentum;
+        P.one.bg = c.background;
         P.one.eps = c.ridge;
         P.one.p = c.pixels;
         P.one.b = h->wb;
@@ -420,19 +426,27 @@ int erx_labels(erx_ctx* h, float tau, unsigned char* out)
 int erx_get_state(erx_ctx* h, long long* t, double* mu, double* K)
 {
     if (!h) return fail(ERX_EINVAL, "NULL handle");
-    std::vector<double> s(h->E);
-    HIPCHK(hipMemcpyAsync(s.data(), h->state, h->E * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> s(h->E + h->bpad);
+    HIPCHK(hipMemcpyAsync(s.data(), h->state, s.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     const int b = h->wb, NT = h->NT;
     if (t) *t = h->t;
     std::vector<double> zref;
     HIPCHK(srp_zref(h, zref));
+    const double* m = &s[(size_t)h->NTL * 256];
+    const double* cref = &s[h->E];
+    const bool imc = h->cfg.background == ERX_BG_IMC && h->t > 0;
+    // IMC: the state holds second moments about the reference mean; K = N/(N-1) (C - (mu-c)(mu-c)^T)
+    const double N = (double)h->t * h->cfg.pixels, f = imc ? N / (N - 1.0) : 1.0;
     if (mu)
-        for (int j = 0; j < b; ++j) mu[j] = s[(size_t)h->NTL * 256 + j] + zref[j];
+        for (int j = 0; j < b; ++j) mu[j] = m[j] + zref[j];
     if (K)
         for (int r = 0; r < b; ++r)
-            for (int c = 0; c < b; ++c)
-                K[(size_t)r * b + c] = (r <= c) ? s[packed_offset(r, c, NT)] : s[packed_offset(c, r, NT)];
+            for (int c = 0; c < b; ++c) {
+                double v = (r <= c) ? s[packed_offset(r, c, NT)] : s[packed_offset(c, r, NT)];
+                if (imc) v = f * (v - (m[r] - cref[r]) * (m[c] - cref[c]));
+                K[(size_t)r * b + c] = v;
+            }
     return ERX_OK;
 }
 
@@ -441,21 +455,27 @@ int erx_set_state(erx_ctx* h, long long t, const double* mu, const double* K)
     if (!h) return fail(ERX_EINVAL, "NULL handle");
     if (t < 0) return fail(ERX_EINVAL, "t must be >= 0");
     if (t > 0 && (!mu || !K)) return fail(ERX_EINVAL, "mu and K are required when t > 0");
-    std::vector<double> s(h->E, 0.0);
+    std::vector<double> s(h->E + h->bpad, 0.0);
     const int b = h->wb, NT = h->NT;
     if (h->srpW && !h->srp_ref_set) h->srp_ref_set = true;  // the state fixes the reference: x_ref = 0
     std::vector<double> zref;
     HIPCHK(srp_zref(h, zref));
+    // IMC: second moments about the reference c = mu, C = (N-1)/N K
+    const bool imc = h->cfg.background == ERX_BG_IMC && t > 0;
+    const double N = (double)t * h->cfg.pixels, f = imc ? (N - 1.0) / N : 1.0;
     if (t > 0) {
-        for (int j = 0; j < b; ++j) s[(size_t)h->NTL * 256 + j] = mu[j] - zref[j];
+        for (int j = 0; j < b; ++j) {
+            s[(size_t)h->NTL * 256 + j] = mu[j] - zref[j];
+            if (imc) s[h->E + j] = mu[j] - zref[j];
+        }
         for (int r = 0; r < b; ++r)
             for (int c = r; c < b; ++c) {
-                s[packed_offset(r, c, NT)] = K[(size_t)r * b + c];
+                s[packed_offset(r, c, NT)] = f * K[(size_t)r * b + c];
                 // diagonal tiles are stored whole (both triangles), as the kernels write them
-                if ((r >> 4) == (c >> 4)) s[packed_offset(c, r, NT)] = K[(size_t)c * b + r];
+                if ((r >> 4) == (c >> 4)) s[packed_offset(c, r, NT)] = f * K[(size_t)c * b + r];
             }
     }
-    HIPCHK(hipMemcpyAsync(h->state, s.data(), h->E * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->state, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->t = t;
     h->have_scores = false;

@@ -134,7 +134,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     if (!(c.ridge >= 0.0f) || !std::isfinite(c.ridge) || (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16) ||
         c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_FP16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1) ||
-        (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0) {
+        (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
+        c.background != ERX_BG_EMA) {
         fail(ERX_EINVAL, "erx_batch_create: invalid common configuration");
         return nullptr;
     }

@@ -152,6 +152,16 @@ __device__ __forceinline__ StreamDesc stream_of_seg(const Pass& P, int g)
     return load_desc(P.sd + lo);
 }
 
+// Weight of stream line tg (0-based, over the stream's life) in the moving average
+// C_tg = (1 - a) C_{tg-1} + a S_tg: the momentum (Sec. III-C; the first line
+// initialises, a = 1), or 1 / (tg + 1) for the equally weighted IMC background
+// (the running mean of the per-line values).
+__device__ __forceinline__ double avg_weight(const StreamDesc& d, long long tg)
+{
+    if (d.bg == BG_IMC) return 1.0 / (double)(tg + 1);
+    return tg == 0 ? 1.0 : d.alpha;
+}
+
 __device__ __forceinline__ long long tile_u(int I, int J, int NT)  // upper tile I <= J
 {
     return (long long)I * NT - (long long)I * (I - 1) / 2 + (J - I);

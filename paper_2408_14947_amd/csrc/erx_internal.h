@@ -8,6 +8,7 @@
 namespace erx {
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_U16 = 2 };
+enum { BG_EMA = 0, BG_IMC = 1 };
 enum { FLAG_NEED_FP64 = 1, FLAG_FP64_DONE = 2, FLAG_NOTPD = 4, FLAG_SCORE32 = 8 };
 
 constexpr int MAX_NT = 19;   // 16-band tiles: up to 304 bands
@@ -35,7 +36,8 @@ struct StreamDesc {
     int n;            // lines of the stream in this pass
     int line0;        // index of its first line in the pass
     int seg0;         // index of its first scan segment in the pass
-    int pad_;
+    int bg;           // BG_EMA, or BG_IMC (equal weights: statistics hold second moments about
+                      // the reference mean kept after the state, see k_imc_moments)
 };
 
 struct Pass {
@@ -53,6 +55,8 @@ struct Pass {
 
 hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s);
+// IMC: per-line statistics (K_hat, mu_hat) -> second moments about the stream's reference mean
+hipError_t launch_imc_moments(const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s);
 // fp64 = 1: FP64 factorisation of every line (force = 1) or of the lines the
 // FP32 pass flagged (force = 0).  fp64 = 0: FP32 factorisation; force = 1

@@ -528,7 +528,6 @@ __global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __rest
     const StreamDesc d = stream_of_seg(P, gsg);
     const int l0 = (gsg - d.seg0) * P.seg;  // stream-local first line
     const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
-    const double alpha = d.alpha;
     const long long t0 = d.t0;
     double* ptr = stats + (size_t)d.line0 * E + e;
     double acc = 0.0;
@@ -539,7 +538,7 @@ __global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __rest
         for (int q = 0; q < 8; ++q) v[q] = ptr[(size_t)(l + q) * E];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const double a = (t0 + l + q == 0) ? 1.0 : alpha;
+            const double a = avg_weight(d, t0 + l + q);
             acc = (1.0 - a) * acc + a * v[q];
             v[q] = acc;
         }
@@ -547,16 +546,46 @@ __global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __rest
         for (int q = 0; q < 8; ++q) ptr[(size_t)(l + q) * E] = v[q];
     }
     for (; l < l1; ++l) {
-        const double a = (t0 + l == 0) ? 1.0 : alpha;
+        const double a = avg_weight(d, t0 + l);
         acc = (1.0 - a) * acc + a * ptr[(size_t)l * E];
         ptr[(size_t)l * E] = acc;
     }
 }
 
-__device__ __forceinline__ double seg_decay(long long t0, int l0, int l1, double alpha)
+// IMC (equally weighted background): the statistics of line j become its second
+// moments about the stream's reference mean c, X_j = ((p-1)/p) K_hat_j +
+// (mu_hat_j - c)(mu_hat_j - c)^T = (1/p) sum over its pixels of (x-c)(x-c)^T, so that
+// their running mean over lines is (1/N) sum over all pooled pixels.  c is the
+// first line's mean, stored after the state when the stream starts.  The mean
+// entries are left as they are (their running mean is the pooled mean).
+__global__ __launch_bounds__(256) void k_imc_moments(const Pass P, double* __restrict__ stats, long long E, int NT)
+{
+    const int line = blockIdx.y;
+    const StreamDesc d = stream_of_line(P, line);
+    const long long ntU = (long long)NT * (NT + 1) / 2;
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    const double* mu0 = stats + (size_t)d.line0 * E + ntU * 256;  // the pass's first line of the stream
+    const bool fresh = d.t0 == 0;
+    const double* c = fresh ? mu0 : d.state + E;
+    double* ls = stats + (size_t)line * E;
+    if (fresh && line == d.line0 && e < 16 * NT) d.state[E + e] = mu0[e];
+    if (e >= ntU * 256) return;
+    int u = (int)(e >> 8), I = 0;
+    while (u >= NT - I) {
+        u -= NT - I;
+        ++I;
+    }
+    const int J = I + u, pos = (int)(e & 255), q = pos >> 2;
+    const int r = 16 * I + 4 * (q >> 4) + (pos & 3), cc = 16 * J + (q & 15);
+    const double* mh = ls + ntU * 256;
+    const double pf = (double)(d.p - 1) / (double)d.p;
+    ls[e] = (r < d.b && cc < d.b) ? pf * ls[e] + (mh[r] - c[r]) * (mh[cc] - c[cc]) : 0.0;
+}
+
+__device__ __forceinline__ double seg_decay(const StreamDesc& d, long long t0, int l0, int l1)
 {
     double P = 1.0;
-    for (int l = l0; l < l1; ++l) P *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
+    for (int l = l0; l < l1; ++l) P *= 1.0 - avg_weight(d, t0 + l);
     return P;
 }
 
@@ -571,7 +600,7 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
     const int nseg = (d.n + P.seg - 1) / P.seg;
     // decay over a whole segment that does not hold the stream's first line
     // (the same product as seg_decay); other segments take seg_decay
-    const double full = seg_decay(1, 0, P.seg, d.alpha);
+    const double full = seg_decay(d, 1, 0, P.seg);  // used for EMA streams only
     // the segment end values are read eight at a time ahead of the serial chain
     constexpr int U = 8;
     for (int g0 = 0; g0 < nseg; g0 += U) {
@@ -589,8 +618,8 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
                 carry[(size_t)(d.seg0 + gs) * E + e] = cv;
                 const int l0 = gs * P.seg;
                 const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
-                const bool whole = l1 - l0 == P.seg && d.t0 + l0 > 0;
-                cv = (whole ? full : seg_decay(d.t0, l0, l1, d.alpha)) * cv + ev[u];
+                const bool whole = l1 - l0 == P.seg && d.t0 + l0 > 0 && d.bg == BG_EMA;
+                cv = (whole ? full : seg_decay(d, d.t0, l0, l1)) * cv + ev[u];
             }
         }
     }
@@ -642,7 +671,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     if (line >= P.nlines) return;
     const StreamDesc sdl = stream_of_line(P, line);
     const int b = sdl.b, seg = P.seg;
-    const double eps = sdl.eps, alpha = sdl.alpha;
+    const double eps = sdl.eps;
     const long long t0 = sdl.t0;
     // the FP64 instantiation factors every line (force) or the lines the FP32 pass flagged
     if (FB && !force && !(flags[line] & FLAG_NEED_FP64)) return;  // uniform for the workgroup
@@ -660,7 +689,7 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     const int lloc = line - sdl.line0;  // stream-local line index
     const int gseg = sdl.seg0 + lloc / seg, l0 = (lloc / seg) * seg;
     double D = 1.0;
-    for (int l = l0; l <= lloc; ++l) D *= (t0 + l == 0) ? 0.0 : (1.0 - alpha);
+    for (int l = l0; l <= lloc; ++l) D *= 1.0 - avg_weight(sdl, t0 + l);
     if (tid == 0) {
         fail_s = 0;
         mmax_s = 0u;
@@ -671,6 +700,15 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     int tI[SLOTS], tJ[SLOTS];
     const double* st = stats + (size_t)line * E;
     const double* cr = carry + (size_t)gseg * E;
+    // IMC: the averaged statistics are second moments about the reference mean c
+    // (kept after the stream's state); the sample covariance of the N = t p pooled
+    // pixels is N / (N - 1) (C - (mu - c)(mu - c)^T)
+    const bool imc = sdl.bg == BG_IMC;
+    const double* cref = sdl.state + E;
+    const double nfac = imc ? (double)((t0 + lloc + 1) * sdl.p) / (double)((t0 + lloc + 1) * sdl.p - 1) : 1.0;
+    auto mean_at = [&](int q) __attribute__((always_inline)) {
+        return st[(long long)NTL * 256 + q] + D * cr[(long long)NTL * 256 + q];
+    };
 #pragma unroll
     for (int j = 0; j < SLOTS; ++j) {
         const int s = j * NW + w;
@@ -690,6 +728,8 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
                 const long long o = u + (16 * (row >> 2) + c) * 4 + (row & 3);
                 double v = st[o] + D * cr[o];
                 const int rb = 16 * J + row, cb = 16 * I + c;
+                if (imc && rb < b && cb < b)
+                    v = nfac * (v - (mean_at(rb) - glb(cref)[rb]) * (mean_at(cb) - glb(cref)[cb]));
                 if (rb == cb) v += eps;
                 if (rb >= b || cb >= b) v = (rb == cb) ? 1.0 : 0.0;
                 A[j][i] = (T)v;
@@ -1266,6 +1306,14 @@ hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s
     const long long E = stat_entries(NT);
     dim3 g1((unsigned)((E + 255) / 256), (unsigned)P.nseg);
     hipLaunchKernelGGL(k_scan_local, g1, dim3(256), 0, s, P, stats, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_imc_moments(const Pass& P, int NT, double* stats, hipStream_t s)
+{
+    const long long E = stat_entries(NT);
+    dim3 g((unsigned)(((long long)NT * (NT + 1) / 2 * 256 + 255) / 256), (unsigned)P.nlines);
+    hipLaunchKernelGGL(k_imc_moments, g, dim3(256), 0, s, P, stats, E, NT);
     return hipGetLastError();
 }
 

@@ -80,6 +80,8 @@ hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, i
     auto T = [&](int k, auto&& f) -> hipError_t { return prof ? prof->timed(s, k, f) : f(); };
     hipError_t e;
     if ((e = T(K_GRAM, [&] { return launch_gram(dtype, prec, P, NT, stats, s); })) != hipSuccess) return e;
+    if (P.nstreams == 1 && !P.sd && P.one.bg == BG_IMC)
+        if ((e = launch_imc_moments(P, NT, stats, s)) != hipSuccess) return e;
     if ((e = T(K_SCAN_LOCAL, [&] { return launch_scan_local(P, NT, stats, s); })) != hipSuccess) return e;
     if ((e = T(K_SCAN_CARRY, [&] { return launch_scan_carry(P, NT, stats, carry, s); })) != hipSuccess) return e;
     if (thr > 0.0) {
