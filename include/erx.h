@@ -382,6 +382,28 @@ typedef struct erx_detection_metrics_t {
 ERX_API int erx_detection_metrics(const float *scores, const unsigned char *truth, long long n, void *hip_stream,
                                   erx_detection_metrics_t *out);
 
+/* ---------------------------------------------------------------------------------------
+ * RX Baseline, the reference detector the paper compares ERX with (Sec. IV-B): a rolling
+ * buffer holds the last `window` lines (the paper: 99); the mean and the covariance
+ * (divisor n, the RX definition of Sec. II-A) of all pixels in the buffer, plus cfg->ridge
+ * on the diagonal (0 gives the RX definition; the ERX default 1e-5 is kept if not changed),
+ * score the buffer's centre line.  The window ending at stream line t (0-based) scores
+ * line t - (window - 1) / 2; the first window is complete once `window` lines arrived, so
+ * the first (window - 1) / 2 lines are never scored, and the last (window - 1) / 2 lines
+ * are scored only by later pushes.  cfg: bands, pixels, ridge, dtype, precision,
+ * fp64_cond_threshold, cond_estimate, score_arith, block_lines and scan_lines as for
+ * erx_create_ex (momentum is unused; srp_dims and normalise must be 0).  window: odd, >= 1.
+ * --------------------------------------------------------------------------------------- */
+typedef struct erx_rxb erx_rxb;
+ERX_API erx_rxb *erx_rxb_create(const erx_config *cfg, int window);
+/* lines: device buffer [n][pixels][bands] in cfg->dtype; stream-ordered */
+ERX_API int erx_rxb_push(erx_rxb *r, const void *lines, int n);
+/* Scores of the centre lines whose windows the last push completed: *nlines lines
+ * [nlines][pixels] from stream line *first_line on (-1 and 0 when none) into out (host or
+ * device, may be NULL to query the count); blocks. */
+ERX_API int erx_rxb_scores(erx_rxb *r, float *out, long long *first_line, int *nlines);
+ERX_API void erx_rxb_destroy(erx_rxb *r);
+
 /* Wait for all work enqueued on the handle's stream. */
 ERX_API int erx_synchronize(erx_ctx *h);
 

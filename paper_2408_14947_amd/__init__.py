@@ -37,7 +37,8 @@ EXPORTS = (
     "erx_surrogate_grads", "erx_surrogate_destroy", "erx_surrogate_detector_create",
     "erx_surrogate_detector_push", "erx_surrogate_detector_scores", "erx_surrogate_detector_status",
     "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup", "erx_push_lines_noalloc",
-    "erx_detection_metrics", "erx_srp_matrix",
+    "erx_detection_metrics", "erx_srp_matrix", "erx_rxb_create", "erx_rxb_push", "erx_rxb_scores",
+    "erx_rxb_destroy",
 )
 SURR_K, SURR_HIDDEN = 16, 64
 
@@ -138,6 +139,10 @@ def load(path: str = LIB_PATH):
         "erx_push_lines_noalloc": (ip, [C.POINTER(Config), vp, C.c_longlong, vp, ip, vp, vp]),
         "erx_detection_metrics": (ip, [vp, vp, C.c_longlong, vp, C.POINTER(DetectionMetrics)]),
         "erx_srp_matrix": (ip, [ip, ip, C.c_ulonglong, vp]),
+        "erx_rxb_create": (vp, [C.POINTER(Config), ip]),
+        "erx_rxb_push": (ip, [vp, vp, ip]),
+        "erx_rxb_scores": (ip, [vp, vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int)]),
+        "erx_rxb_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -461,6 +466,53 @@ def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge:
     return int(t0) + n
 
 
+class RXBaseline:
+    """RX Baseline (rolling window of `window` lines scoring its centre line) on the GPU."""
+
+    def __init__(self, bands: int, pixels: int, window: int = 99, ridge: float = 0.0, dtype: str = "f32",
+                 precision: str = "fp32", fp64_cond_threshold: float = 0.0, block_lines: int = 2048,
+                 scan_lines: int = 64, score_arith: str = "split16"):
+        lib = load()
+        cfg = Config()
+        lib.erx_config_default(C.byref(cfg), int(bands), int(pixels), 0.1)
+        cfg.ridge = float(ridge)
+        cfg.dtype = DTYPES[dtype]
+        cfg.precision = PRECISIONS[precision]
+        cfg.fp64_cond_threshold = float(fp64_cond_threshold)
+        cfg.block_lines = int(block_lines)
+        cfg.scan_lines = int(scan_lines)
+        cfg.score_arith = SCORE_ARITH[score_arith]
+        self._lib = lib
+        self.pixels = int(pixels)
+        self._h = lib.erx_rxb_create(C.byref(cfg), int(window))
+        if not self._h:
+            raise ErxError(ERX_EINVAL, last_error())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.erx_rxb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, lines):
+        _check(self._lib.erx_rxb_push(self._h, C.c_void_p(_ptr(lines)), int(lines.shape[0])))
+        return self
+
+    def scores(self):
+        """(first scored stream line, float32 array [m, pixels]) of the last push."""
+        first, m = C.c_longlong(0), C.c_int(0)
+        _check(self._lib.erx_rxb_scores(self._h, None, C.byref(first), C.byref(m)))
+        out = np.empty((m.value, self.pixels), np.float32)
+        if m.value:
+            _check(self._lib.erx_rxb_scores(self._h, C.c_void_p(out.ctypes.data), C.byref(first), C.byref(m)))
+        return int(first.value), out
+
+
 def srp_matrix(bands: int, dims: int, seed: int) -> np.ndarray:
     """erx_srp_matrix: the projection weights W [bands][dims] a detector with srp_dims =
     dims and srp_seed = seed uses (host computation, no GPU needed)."""
@@ -487,7 +539,7 @@ def detection_metrics(scores, truth, stream: Optional[int] = -1) -> dict:
     return {k: getattr(m, k) for k, _ in DetectionMetrics._fields_}
 
 
-__all__ = ["Detector", "Batch", "detection_metrics", "srp_matrix", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
+__all__ = ["Detector", "Batch", "RXBaseline", "detection_metrics", "srp_matrix", "ErxError", "load", "last_error", "EXPORTS", "DTYPES", "PRECISIONS",
            "FLAG_NEED_FP64", "FLAG_FP64_DONE", "FLAG_NOTPD", "FLAG_SCORE32", "MAX_BANDS", "SCORE_ARITH", "push_lines_noalloc",
            "noalloc_state_entries", "NOALLOC_SCRATCH_BYTES"]
 

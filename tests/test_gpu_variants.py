@@ -81,3 +81,28 @@ def test_imc_state_round_trip_and_srp(erx):
     want = V.imc_run(Z)
     log(f"  IMC + SRP d=5: max err {rel_err(got, want).max():.3e}")
     assert rel_err(got, want).max() <= TOL
+
+
+@pytest.mark.parametrize("b,p,T,W,ridge,blk,pushes", [(8, 64, 40, 9, 0.0, 2048, 1), (40, 200, 70, 15, 1e-5, 16, 3),
+                                                      (108, 200, 150, 99, 0.0, 64, 2), (224, 160, 120, 99, 0.0, 2048, 1),
+                                                      (30, 100, 12, 1, 0.0, 5, 1), (20, 50, 30, 5, 0.0, 3, 4)])
+def test_rx_baseline_matches_reference(erx, b, p, T, W, ridge, blk, pushes):
+    log(f"RX Baseline b={b} p={p} T={T} window={W} ridge={ridge} block_lines={blk} pushes={pushes}")
+    scene = datagen.make_scene(53, b, b, p, T, drift=True)
+    X, _ = datagen.lines(scene, 0, T)
+    det = erx.RXBaseline(b, p, window=W, ridge=ridge, block_lines=blk, scan_lines=8)
+    Xd = X.cuda()
+    cuts = np.linspace(0, T, pushes + 1).astype(int)
+    firsts, outs = [], []
+    for a, c in zip(cuts[:-1], cuts[1:]):
+        det.push(Xd[a:c])
+        f, s = det.scores()
+        if s.shape[0]:
+            firsts.append(f)
+            outs.append(s)
+    got = np.concatenate(outs)
+    first, want = V.rx_baseline_run(X.numpy(), window=W, ridge=ridge)
+    err = rel_err(got, want)
+    log(f"  first scored line {firsts[0]} (ref {first}), {got.shape[0]} lines, max err {err.max():.3e}")
+    assert firsts[0] == first and got.shape == want.shape
+    assert err.max() <= TOL
