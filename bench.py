@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = "ERX pixels/s + lines/s at 108/224 bands; mixed/batched vs plain FP32 at stated err"
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 # sources of the kernels the long-scan workload runs (the traffic record is tied to them)
-KERNEL_SRC = [os.path.join(ROOT, "paper_2408_14947_amd", "csrc", f) for f in ("erx_kernels.hip", "erx_device.h")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_2408_14947_amd", "csrc", f)
+              for f in ("erx_kernels.hip", "erx_device.h", "erx_score16.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_long-scan-224.md")
 WORKLOAD = ("long-scan-224: one stream, 20000 lines x 1024 px x 224 bands, f32, momentum 0.1, "
             "ridge 1e-5, drifting 4-endmember mixture, 0.2% 3x3 patches")
@@ -206,16 +207,21 @@ def tune_leg(erx, torch, X, b, p, momentum, args, stream, ms_default):
     return res
 
 
-def batched_leg(erx, torch, cfg, T, stream, mixed):
-    """Many independent streams of one workload configuration (each cut to T lines): the batched
-    path (shared passes, graph replay) against one handle per stream pushed one after another,
-    and optionally the mixed configuration (BF16 Gram, FP32 Cholesky with FP64 re-factor above a
-    condition estimate of 1e6) with its per-stream error against the plain batched scores."""
+def batched_leg(erx, torch, cfg, T, stream, mixed, n_check):
+    """Many independent streams of one workload configuration, each cut to T lines (0: the
+    configured lengths): the batched path (shared passes, graph replay) against one handle per
+    stream, each pushed and timed in turn.  Each is timed on its second push of the same
+    lines (graphs captured and states warm).  The score error against the FP64 oracle is
+    taken on n_check sampled streams (the one with the most bands x pixels included);
+    optionally the mixed configuration (BF16 Gram, FP32 Cholesky with FP64 re-factor above
+    a condition estimate of 1e6) with the same checks."""
+    import numpy as np
     import datagen
-    scenes = datagen.config_scenes(cfg, scale_lines=T)
+    scenes = datagen.config_scenes(cfg, scale_lines=T if T > 0 else None)
     storage = scenes[0].storage
+    print(f"[bench] generating {datagen.CONFIGS[cfg]['name']}: {len(scenes)} streams", file=sys.stderr, flush=True)
     with torch.cuda.stream(stream):
-        data = [datagen.lines(sc, 0, sc.lines, device="cuda")[0] for sc in scenes]
+        data = [datagen.lines(sc, 0, sc.lines, device="cuda", span=2048)[0] for sc in scenes]
     torch.cuda.synchronize()
     B = [sc.bands for sc in scenes]
     Pp = [sc.pixels for sc in scenes]
@@ -223,6 +229,9 @@ def batched_leg(erx, torch, cfg, T, stream, mixed):
     n_lines = sum(x.shape[0] for x in data)
     n_pix = sum(x.shape[0] * x.shape[1] for x in data)
     in_bytes = sum(x.numel() * x.element_size() for x in data)
+    rng = np.random.default_rng(7 + cfg)
+    big = int(np.argmax([b_ * p_ for b_, p_ in zip(B, Pp)]))
+    check = sorted({big, *rng.choice(len(scenes), size=min(n_check, len(scenes)) - 1, replace=False).tolist()})
 
     def timed(fn):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -234,46 +243,77 @@ def batched_leg(erx, torch, cfg, T, stream, mixed):
         return ev0.elapsed_time(ev1)
 
     def run_batch(**kw):
+        """First push from a fresh state (captures the pass graphs), then the same lines again
+        (graph replay; the states continue): the second push is timed."""
         bt = erx.Batch(B, Pp, A, dtype=storage, block_lines=8192, stream=stream.cuda_stream, **kw)
-        bt.push(data)  # warm-up: captures the pass graphs
+        bt.push(data)
+        first = bt.scores(streams=check)
+        first = {s_: first[s_][:32].clone() for s_ in check}
         torch.cuda.synchronize()
-        bt2 = erx.Batch(B, Pp, A, dtype=storage, block_lines=8192, stream=stream.cuda_stream, **kw)
-        bt2.push(data)
-        torch.cuda.synchronize()
-        ms = timed(lambda: bt2.push(data))  # same lines again: the state continues, the work is the same
-        out = bt2.scores()
+        ms = timed(lambda: bt.push(data))
+        second = bt.scores(streams=check)
+        second = {s_: second[s_][-32:].clone() for s_ in check}
         torch.cuda.synchronize()
         bt.close()
-        bt2.close()
-        return ms, out
+        return ms, (first, second)
+
+    def check_streams(sc_pair):
+        """First 32 lines of the first push against the oracle from line 0 (exact), last 32
+        lines of the second push (stream lines 2T-32..2T-1 of the data pushed twice) against
+        the oracle started fresh 25 / momentum lines earlier."""
+        import datagen as dg
+        import oracle
+        first, second = sc_pair
+        per = []
+        for s_ in check:
+            sc, x = scenes[s_], data[s_]
+            Tn = x.shape[0]
+            k = min(32, Tn)
+            want0 = oracle.run(dg.storage_to_float64(x[:k], storage), sc.momentum, 1e-5)["delta"]
+            warm = int(np.ceil(25.0 / sc.momentum))
+            a = max(0, 2 * Tn - k - warm)  # window start in the twice-pushed stream
+            parts = ([x[a:Tn]] if a < Tn else []) + [x[max(a - Tn, 0):Tn]]
+            xw = dg.storage_to_float64(torch.cat(parts), storage)
+            want1 = oracle.run(xw, sc.momentum, 1e-5)["delta"][-k:]
+            got = np.concatenate([first[s_][:k].double().cpu().numpy(), second[s_][-k:].double().cpu().numpy()])
+            e = err_stats(got, np.concatenate([want0, want1]))
+            per.append(dict(stream=s_, bands=sc.bands, pixels=sc.pixels, lines=Tn,
+                            momentum=round(sc.momentum, 4), oracle_window_lines=int(xw.shape[0]), **e))
+        return per
 
     ms_b, ref = run_batch()
-    dets = [erx.Detector(b, p, a, dtype=storage, block_lines=max(x.shape[0], 1), stream=stream.cuda_stream)
-            for b, p, a, x in zip(B, Pp, A, data)]
-    for d, x in zip(dets, data):
-        d.push(x)
-    ms_1 = timed(lambda: [d.push(x) for d, x in zip(dets, data)])
-    for d in dets:
+    per_plain = check_streams(ref)
+    del ref
+    # one handle per stream, pushed one after another (each timed alone, summed)
+    ms_1 = 0.0
+    for b_, p_, a_, x in zip(B, Pp, A, data):
+        d = erx.Detector(b_, p_, a_, dtype=storage, block_lines=min(max(x.shape[0], 1), 4096),
+                         stream=stream.cuda_stream)
+        d.push(x)  # first push, then the same lines again, timed
+        ms_1 += timed(lambda: d.push(x))
         d.close()
-    res = {"workload": f"{datagen.CONFIGS[cfg]['name']}: {len(scenes)} streams x {T} lines, {storage}",
-           "streams": len(scenes), "lines": n_lines, "pixels": n_pix, "input_bytes": in_bytes,
+    name = datagen.CONFIGS[cfg]["name"]
+    res = {"workload": f"{name}: {len(scenes)} streams x " + (f"{T} lines (cap)" if T > 0 else "configured lengths")
+                       + f", {storage}",
+           "lines_per_stream": T if T > 0 else "configured", "streams": len(scenes), "lines": n_lines,
+           "pixels": n_pix, "input_bytes": in_bytes,
            "batched": {"ms": ms_b, "lines_per_s": n_lines / (ms_b / 1e3), "pixels_per_s": n_pix / (ms_b / 1e3),
                        "hbm_gbs_in_plus_scores": (in_bytes + 4 * n_pix) / (ms_b / 1e3) / 1e9},
            "one_handle_per_stream": {"ms": ms_1, "lines_per_s": n_lines / (ms_1 / 1e3),
                                      "pixels_per_s": n_pix / (ms_1 / 1e3)},
-           "batched_speedup": ms_1 / ms_b}
+           "batched_speedup": ms_1 / ms_b,
+           "err_vs_oracle_per_stream": per_plain,
+           "err_vs_oracle_worst": {k: max(r[k] for r in per_plain) for k in ("max", "p99", "median")}}
     res["batched"]["hbm_frac"] = res["batched"]["hbm_gbs_in_plus_scores"] / PEAK["hbm_gbs"]
     if mixed:
         ms_m, got = run_batch(precision="bf16", fp64_cond_threshold=1e6, cond_estimate=1)
-        per = []
-        for g, r in zip(got, ref):
-            e = ((g.double() - r.double()).abs() / r.double().abs().clamp_min(1.0)).flatten()
-            k = max(1, e.numel() // 100)
-            per.append((float(e.max()), float(torch.topk(e, k).values.min())))
+        per = check_streams(got)
+        del got
         res["mixed_bf16"] = {"ms": ms_m, "pixels_per_s": n_pix / (ms_m / 1e3), "speedup_vs_batched_plain": ms_b / ms_m,
-                             "err_vs_plain_worst_stream": {"max": max(a for a, _ in per), "p99": max(b for _, b in per)},
+                             "err_vs_oracle_per_stream": per,
+                             "err_vs_oracle_worst": {k: max(r[k] for r in per) for k in ("max", "p99", "median")},
                              "bound": {"max": MIXED_BOUNDS["bf16"][0], "p99": MIXED_BOUNDS["bf16"][1]}}
-    del data, ref
+    del data
     torch.cuda.empty_cache()
     return res
 
@@ -401,14 +441,95 @@ def surrogate_leg(erx, torch, stream, steps):
     return res
 
 
+def err_stats(got, want):
+    """max / p99 / median of |got - want| / max(|want|, 1) over all pixels given."""
+    import numpy as np
+    e = (np.abs(np.asarray(got, np.float64) - want) / np.maximum(np.abs(want), 1.0)).ravel()
+    return {"max": float(e.max()), "p99": float(np.quantile(e, 0.99)), "median": float(np.median(e)),
+            "checked_pixels": int(e.size)}
+
+
+def oracle_windows(X, storage, momentum, ends, check=32, warm=256):
+    """FP64 oracle scores of the `check` lines before each end, each window started fresh
+    `warm` lines earlier (from line 0 when that is closer).  A fresh start differs from the
+    true background by a weight of (1 - momentum)^warm, far below the error bound once
+    warm >= 25 / momentum; windows that start at line 0 are exact.  X: device lines as
+    stored; returns {end: float64 [check, p]}."""
+    import datagen
+    import oracle
+    out = {}
+    for L in ends:
+        a = max(0, L - check - warm)
+        xh = datagen.storage_to_float64(X[a:L], storage)
+        out[L] = oracle.run(xh, momentum, 1e-5)["delta"][-check:]
+    return out
+
+
+def oracle_error(scores, X, storage, momentum, ends, check=32, warm=256):
+    """Score error of GPU scores [T, p] against the oracle windows ending at `ends`."""
+    import numpy as np
+    ref = oracle_windows(X, storage, momentum, ends, check, warm)
+    got = np.concatenate([scores[L - check:L].double().cpu().numpy() for L in ends])
+    return err_stats(got, np.concatenate([ref[L] for L in ends]))
+
+
+def cpu_info():
+    import subprocess
+    model = ""
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except Exception:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+SINGLE_THREAD_SNIPPET = r"""
+import sys, time, json
+sys.path.insert(0, sys.argv[1])
+import numpy as np, datagen, oracle
+sc = datagen.config_scenes(2)[0]
+n = int(sys.argv[2])
+X, _ = datagen.lines(sc, 0, n, device="cpu")
+x = X.numpy().astype(np.float64)
+s = oracle.Stream(sc.bands, sc.pixels, sc.momentum, 1e-5, nthreads=1)
+s.push(x[:8])
+t0 = time.perf_counter()
+s.push(x[8:])
+dt = time.perf_counter() - t0
+print(json.dumps({"lines": n - 8, "seconds": dt, "threads": 1}))
+"""
+
+
+def cpu_single_thread(lines=40):
+    """The oracle on one host thread, in a child process."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", SINGLE_THREAD_SNIPPET, ROOT, str(lines)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 # frozen error bounds of the reduced-precision Gram (max, p99 of the relative score error)
 MIXED_BOUNDS = {"bf16": (1e-2, 3e-3), "fp16": (1e-3, 5e-4)}
 
 
-def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof):
+CHECK_ENDS = (32, 5000, 12000, 20000)  # long-scan windows checked against the oracle
+
+
+def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof, ref_windows):
     """BF16 / FP16 Gram with FP32 Cholesky (FP64 re-factor above a condition estimate of 1e6)
-    on the same scan: throughput, and the score error against the plain FP32 GPU path over
-    every pixel of the scan (the plain path is itself within 1e-4 of the FP64 oracle)."""
+    on the same scan: throughput; the score error against the FP64 oracle on the checked
+    windows (32 lines ending at each of CHECK_ENDS), and against the plain GPU path over
+    every pixel of the scan."""
+    import numpy as np
     T = X.shape[0]
 
     def scores(**kw):
@@ -418,6 +539,10 @@ def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof)
         det.synchronize()
         det.close()
         return s
+
+    def vs_oracle(sc):
+        got = np.concatenate([sc[L - 32:L].double().cpu().numpy() for L in CHECK_ENDS])
+        return err_stats(got, np.concatenate([ref_windows[L] for L in CHECK_ENDS]))
 
     with torch.cuda.stream(stream):
         ref = scores()
@@ -439,6 +564,7 @@ def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof)
                      "speedup_vs_plain": plain_ms / (ms / args.steps),
                      "gram_ms": gram_ms, "gram_tflops": flops / (gram_ms / 1e3) / 1e12,
                      "gram_peak_tflops": 2500.0,
+                     "err_vs_oracle": vs_oracle(got),
                      "err_vs_plain": {"max": emax, "p99": p99, "median": emed},
                      "bound": {"max": MIXED_BOUNDS[prec][0], "p99": MIXED_BOUNDS[prec][1]},
                      "fp64_refactors": st["fp64_refactors"], "max_cond": st["max_cond"],
@@ -464,8 +590,10 @@ def main():
                     help="skip the reduced-precision (BF16 / FP16 Gram) side measurement")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the many-stream side measurements (batched-u16, batched-multispectral-f16)")
-    ap.add_argument("--batched-lines", type=int, default=128,
-                    help="lines per stream in the many-stream side measurements")
+    ap.add_argument("--batched-lines", type=int, default=0,
+                    help="lines per stream of the batched-u16 measurement (0: the configured 2000-10000)")
+    ap.add_argument("--multispectral-lines", type=int, default=0,
+                    help="lines per stream of the batched-multispectral-f16 measurement (0: the configured 5000)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-projection surrogate side measurement")
     ap.add_argument("--surrogate-steps", type=int, default=200, help="training steps per band count")
@@ -563,8 +691,22 @@ def main():
         "lines_per_s": lines_s, "wall_s": wall, "roofline": roofline, "kernels": kernels,
         "fp64_refactors": st["fp64_refactors"], "max_cond": st["max_cond"],
     }
+    # the headline path's own scores against the FP64 oracle on the checked windows
+    print("[bench] FP64 oracle on the checked windows", file=sys.stderr, flush=True)
+    ref_windows = oracle_windows(X, "f32", sc.momentum, CHECK_ENDS)
+    det = erx.Detector(b, p, sc.momentum, block_lines=args.block_lines, stream=stream.cuda_stream, **kw)
+    det.push(X)
+    s_plain = det.scores()
+    det.synchronize()
+    det.close()
+    got = np.concatenate([s_plain[L - 32:L].double().cpu().numpy() for L in CHECK_ENDS])
+    out["err_vs_oracle"] = dict(err_stats(got, np.concatenate([ref_windows[L] for L in CHECK_ENDS])),
+                                windows=f"32 lines ending at each of {list(CHECK_ENDS)}; the oracle starts "
+                                        "each window 256 lines earlier (line 0 for the first)",
+                                bound=1e-4)
+    del s_plain
     if not args.no_mixed:
-        out["mixed"] = mixed_leg(erx, torch, X, b, p, sc.momentum, args, stream, ms_step, prof)
+        out["mixed"] = mixed_leg(erx, torch, X, b, p, sc.momentum, args, stream, ms_step, prof, ref_windows)
 
     if not args.no_tune:
         print("[bench] autotuning the launch settings", file=sys.stderr, flush=True)
@@ -587,8 +729,9 @@ def main():
 
     if not args.no_batched:
         print("[bench] many-stream workloads", file=sys.stderr, flush=True)
-        out["batched_u16"] = batched_leg(erx, torch, 3, args.batched_lines, stream, mixed=True)
-        out["batched_multispectral_f16"] = batched_leg(erx, torch, 4, args.batched_lines, stream, mixed=False)
+        out["batched_u16"] = batched_leg(erx, torch, 3, args.batched_lines, stream, mixed=True, n_check=4)
+        out["batched_multispectral_f16"] = batched_leg(erx, torch, 4, args.multispectral_lines, stream, mixed=False,
+                                                       n_check=16)
 
     if not args.no_surrogate:
         print("[bench] learned projection surrogate", file=sys.stderr, flush=True)
@@ -607,9 +750,14 @@ def main():
             t_cpu += time.perf_counter() - t0
             done += 32
         cl = done / t_cpu
+        one = cpu_single_thread()
+        l1 = one["lines"] / one["seconds"]
         out["cpu_baseline"] = {"value": cl * p, "unit": "pixels/s", "lines_per_s": cl,
                                "cores": oracle.max_threads(), "kind": "oracle",
-                               "sample": f"first {done} lines of the same 20000-line scan"}
+                               "sample": f"first {done} lines of the same 20000-line scan",
+                               "single_thread": {"value": l1 * p, "lines_per_s": l1, "threads": one["threads"],
+                                                 "sample": f"{one['lines']} lines of the same scan shape"},
+                               "cpu": cpu_info()}
     print(json.dumps(out))
 
 

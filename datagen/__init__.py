@@ -153,15 +153,18 @@ def _uniform_hash(seed: int, a: np.ndarray, c: np.ndarray) -> np.ndarray:
     return (_splitmix64(key) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
 
 
-def _block(scene: Scene, blk: int, device: torch.device):
-    """Lines [blk*BLOCK, (blk+1)*BLOCK) as float32 plus bool mask."""
-    n = min(BLOCK, scene.lines - blk * BLOCK) if scene.lines > 0 else BLOCK
+def _block(scene: Scene, blk: int, device: torch.device, span: int = BLOCK):
+    """Lines [blk*span, (blk+1)*span) as float32 plus bool mask.  The default span is
+    BLOCK; a longer span draws more lines per generator key (fewer, larger calls for
+    whole streams), from a key space of its own."""
+    n = min(span, scene.lines - blk * span) if scene.lines > 0 else span
     n = max(n, 0)
     p, b = scene.pixels, scene.bands
     g = torch.Generator(device=device)
-    g.manual_seed(_seed(scene.cfg, scene.stream, 1000003 + blk))
+    g.manual_seed(_seed(scene.cfg, scene.stream, 1000003 + blk) if span == BLOCK
+                  else _seed(scene.cfg, scene.stream, 2000003, span, blk))
     f32 = dict(device=device, dtype=torch.float32)
-    t = np.arange(blk * BLOCK, blk * BLOCK + n, dtype=np.float64)
+    t = np.arange(blk * span, blk * span + n, dtype=np.float64)
     E = torch.as_tensor(scene.endmembers, **f32)
     F = torch.as_tensor(scene.factor, **f32)
     A = torch.as_tensor(scene.anomalies, **f32)
@@ -192,12 +195,13 @@ def _block(scene: Scene, blk: int, device: torch.device):
     return x, mask
 
 
-def lines(scene: Scene, t0: int, n: int, device="cpu", storage: Optional[str] = None):
+def lines(scene: Scene, t0: int, n: int, device="cpu", storage: Optional[str] = None, span: int = BLOCK):
     """Lines [t0, t0+n) of a stream.
 
     Returns (X, mask): X has shape [n, p, b] in the stream's storage type
     (float32, float16, or uint16 raw counts whose value is u * 2**-16) and mask
-    is a bool [n, p] tensor marking anomalous pixels.
+    is a bool [n, p] tensor marking anomalous pixels.  span: lines per generator
+    key (BLOCK by default; a different span gives a different, equally valid draw).
     """
     device = torch.device(device)
     storage = storage or scene.storage
@@ -205,11 +209,11 @@ def lines(scene: Scene, t0: int, n: int, device="cpu", storage: Optional[str] = 
         X = torch.empty((0, scene.pixels, scene.bands), dtype=torch.float32, device=device)
         return to_storage(X, storage), torch.zeros((0, scene.pixels), dtype=torch.bool, device=device)
     xs, ms = [], []
-    b0, b1 = t0 // BLOCK, (t0 + n - 1) // BLOCK
+    b0, b1 = t0 // span, (t0 + n - 1) // span
     for blk in range(b0, b1 + 1):
-        x, m = _block(_unbounded(scene), blk, device)
-        lo = max(t0 - blk * BLOCK, 0)
-        hi = min(t0 + n - blk * BLOCK, BLOCK)
+        x, m = _block(_unbounded(scene), blk, device, span)
+        lo = max(t0 - blk * span, 0)
+        hi = min(t0 + n - blk * span, span)
         xs.append(x[lo:hi])
         ms.append(m[lo:hi])
     X = torch.cat(xs) if len(xs) > 1 else xs[0]

@@ -214,7 +214,8 @@ ERX_API int erx_batch_set_stream(erx_batch *bt, void *hip_stream);
 /* lines[s]: device buffer [nlines[s]][pixels[s]][bands[s]] (ignored when nlines[s] == 0) */
 ERX_API int erx_batch_push(erx_batch *bt, const void *const *lines, const int *nlines);
 /* out[s]: buffer of nlines[s] * pixels[s] floats (host or device) receiving the scores of
- * stream s's lines of the last push; blocks.  ERX_ENOTPD as for erx_scores. */
+ * stream s's lines of the last push, or NULL to skip stream s; blocks.  ERX_ENOTPD as for
+ * erx_scores. */
 ERX_API int erx_batch_scores(erx_batch *bt, float *const *out);
 ERX_API int erx_batch_get_state(erx_batch *bt, int stream, long long *t, double *mu, double *K);
 ERX_API int erx_batch_stats(erx_batch *bt, erx_stats_t *out);

@@ -398,11 +398,13 @@ class Batch:
         _check(self._lib.erx_batch_push(self._h, ptrs, cnt))
         self.last_n = [int(cnt[s]) for s in range(ns)]
 
-    def scores(self, allow_notpd: bool = True):
-        """Scores of the last push: one float32 CUDA tensor [n_s, pixels_s] per stream (None if 0)."""
+    def scores(self, allow_notpd: bool = True, streams=None):
+        """Scores of the last push: one float32 CUDA tensor [n_s, pixels_s] per stream (None if 0,
+        or if streams is given and does not list s)."""
         import torch
-        outs = [torch.empty((n, p), dtype=torch.float32, device="cuda") if n else None
-                for n, p in zip(self.last_n, self.pixels)]
+        want = None if streams is None else set(int(s) for s in streams)
+        outs = [torch.empty((n, p), dtype=torch.float32, device="cuda") if n and (want is None or s in want) else None
+                for s, (n, p) in enumerate(zip(self.last_n, self.pixels))]
         arr = (C.c_void_p * self.nstreams)(*[(o.data_ptr() if o is not None else None) for o in outs])
         torch.cuda.synchronize()
         _check(self._lib.erx_batch_scores(self._h, arr), allow=(ERX_ENOTPD,) if allow_notpd else ())

@@ -426,8 +426,7 @@ int erx_batch_scores(erx_batch* bt, float* const* out)
     if (!bt || !out) return fail(ERX_EINVAL, "NULL argument");
     for (size_t s = 0; s < bt->st.size(); ++s) {
         const BStream& B = bt->st[s];
-        if (B.last_n == 0) continue;
-        if (!out[s]) return fail(ERX_EINVAL, "stream %zu: NULL output", s);
+        if (B.last_n == 0 || !out[s]) continue;  // a NULL buffer skips the stream
         HIPCHK(hipMemcpyAsync(out[s], B.scores, (size_t)B.last_n * B.p * sizeof(float), hipMemcpyDefault,
                               bt->stream));
     }
