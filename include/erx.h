@@ -63,7 +63,12 @@ enum { ERX_F32 = 0, ERX_F16 = 1, ERX_U16 = 2 /* raw counts u, value u * 2^-16 */
 enum {
     ERX_GRAM_FP32 = 0, /* FP32 matrix cores, FP32 partials per <=64-pixel chunk, FP64 sums */
     ERX_GRAM_BF16 = 1, /* BF16 inputs on the matrix cores, FP32 accumulate */
-    ERX_GRAM_FP16 = 2  /* FP16 inputs on the matrix cores, FP32 accumulate */
+    ERX_GRAM_FP16 = 2, /* FP16 inputs on the matrix cores, FP32 accumulate */
+    ERX_GRAM_SPLIT16 = 3 /* FP16 matrix cores with each value, scaled by a per-band power of two,
+                            split into two FP16 halves (three products, FP32 partials per 64
+                            pixels, FP64 sums): FP32-class accuracy.  A 64x64 block of the Gram
+                            whose values exceed the split's range (128 times the first 64
+                            pixels' spread, or a band constant over them) is recomputed in FP32 */
 };
 
 /* arithmetic of the score product L^{-1}(x - mu) (Sec. III-D) */
@@ -116,7 +121,7 @@ enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };
 
 #define ERX_MAX_BANDS 304
 
-/* Fill *cfg with defaults: ridge 1e-5, warmup 0, F32 input, FP32 Gram,
+/* Fill *cfg with defaults: ridge 1e-5, warmup 0, F32 input, split-FP16 Gram,
  * threshold 0 (FP64 factorisation), no normalisation, block_lines 2048,
  * scan_lines 64, cond_estimate -1, split-FP16 score. */
 ERX_API void erx_config_default(erx_config *cfg, int bands, int pixels, float momentum);

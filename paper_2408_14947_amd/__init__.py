@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liberx.so")
 
 ERX_OK, ERX_EINVAL, ERX_ENOMEM, ERX_EDEVICE, ERX_ENOTPD, ERX_ESTATE = 0, -1, -2, -3, -4, -5
 DTYPES = {"f32": 0, "f16": 1, "u16": 2}
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "split16": 3}
 SCORE_ARITH = {"split16": 0, "fp32": 1}
 BACKGROUNDS = {"ema": 0, "imc": 1}
 FLAG_NEED_FP64, FLAG_FP64_DONE, FLAG_NOTPD, FLAG_SCORE32 = 1, 2, 4, 8
@@ -189,7 +189,7 @@ class Detector:
     """One ERX stream on the current GPU (a handle of the C library)."""
 
     def __init__(self, bands: int, pixels: int, momentum: float = 0.1, ridge: float = 1e-5,
-                 dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
+                 dtype: str = "f32", precision: str = "split16", fp64_cond_threshold: float = 0.0,
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
                  scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
                  score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0,
@@ -334,7 +334,7 @@ class Batch:
     """Many independent streams (one detector each) processed in shared device passes."""
 
     def __init__(self, bands, pixels, momentum, ridge: float = 1e-5, dtype: str = "f32",
-                 precision: str = "fp32",
+                 precision: str = "split16",
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
                  scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True, score_arith: str = "split16",
                  stream: Optional[int] = -1, small_path: int = -1):
@@ -442,7 +442,7 @@ def noalloc_state_entries(bands: int) -> int:
 
 
 def push_lines_noalloc(lines, out, state, t0: int, momentum: float = 0.1, ridge: float = 1e-5,
-                       dtype: str = "f32", precision: str = "fp32", fp64_cond_threshold: float = 0.0,
+                       dtype: str = "f32", precision: str = "split16", fp64_cond_threshold: float = 0.0,
                        block_lines: int = 2048, scan_lines: int = 64, cond_estimate: int = -1,
                        stream: Optional[int] = -1, score_arith: str = "split16") -> int:
     """erx_push_lines_noalloc: score lines [n, pixels, bands] (device tensor) into out
@@ -472,7 +472,7 @@ class RXBaseline:
     """RX Baseline (rolling window of `window` lines scoring its centre line) on the GPU."""
 
     def __init__(self, bands: int, pixels: int, window: int = 99, ridge: float = 0.0, dtype: str = "f32",
-                 precision: str = "fp32", fp64_cond_threshold: float = 0.0, block_lines: int = 2048,
+                 precision: str = "split16", fp64_cond_threshold: float = 0.0, block_lines: int = 2048,
                  scan_lines: int = 64, score_arith: str = "split16"):
         lib = load()
         cfg = Config()
@@ -567,7 +567,7 @@ def _tune_dict(r):
             "candidates": r.candidates, "us_per_line": r.us_per_line}
 
 
-def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32", precision: str = "fp32",
+def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32", precision: str = "split16",
              fp64_cond_threshold: float = 0.0, normalise: bool = False, nstreams: int = 1,
              cache: Optional[str] = None) -> dict:
     """Fastest launch setting for a workload shape (erx_autotune): block_lines, scan_lines,
@@ -580,7 +580,7 @@ def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32",
 
 
 def tune_lookup(bands: int, pixels: int, cache: str, momentum: float = 0.1, dtype: str = "f32",
-                precision: str = "fp32", fp64_cond_threshold: float = 0.0, normalise: bool = False,
+                precision: str = "split16", fp64_cond_threshold: float = 0.0, normalise: bool = False,
                 nstreams: int = 1) -> Optional[dict]:
     """Cached setting for a workload shape (erx_tune_lookup), or None when the cache has none."""
     lib = load()

@@ -46,6 +46,7 @@ struct erx_ctx {
     float* Mt = nullptr;       // [C][NTL][256] inverse-factor tiles
     float* mu32 = nullptr;     // [C][bpad] background mean per line
     float* mscale = nullptr;   // [C] max |L^{-1}| per line (split-FP16 score)
+    int* gredo = nullptr;      // [C][GRAM_MACROS_MAX] split-FP16 Gram blocks left to FP32
     unsigned long long* ctr = nullptr;  // fp64 re-factors, not-PD lines, max cond (float bits)
     int* flags = nullptr;      // [cap] per line of the last push
     float* cond = nullptr;     // [cap]
@@ -74,7 +75,7 @@ namespace {
 
 void free_all(erx_ctx* h)
 {
-    void* ptrs[] = {h->state, h->stats, h->carry, h->Mt, h->mu32, h->mscale, h->ctr, h->flags, h->cond,
+    void* ptrs[] = {h->state, h->stats, h->carry, h->Mt, h->mu32, h->mscale, h->gredo, h->ctr, h->flags, h->cond,
                     h->scores, h->scores_n, h->labels, h->staging, h->srpW, h->zbuf, h->srp_xref};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -161,7 +162,7 @@ void erx_config_default(erx_config* cfg, int bands, int pixels, float momentum)
     cfg->ridge = 1e-5f;
     cfg->warmup = 0;
     cfg->dtype = ERX_F32;
-    cfg->precision = ERX_GRAM_FP32;
+    cfg->precision = ERX_GRAM_SPLIT16;
     cfg->fp64_cond_threshold = 0.0;
     cfg->normalise = 0;
     cfg->block_lines = 2048;
@@ -197,7 +198,7 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "unknown dtype %d", c.dtype);
         return nullptr;
     }
-    if (c.precision != ERX_GRAM_FP32 && c.precision != ERX_GRAM_BF16 && c.precision != ERX_GRAM_FP16) {
+    if (c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16) {
         fail(ERX_EINVAL, "unknown precision %d", c.precision);
         return nullptr;
     }
@@ -247,6 +248,7 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
          dmalloc(&h->Mt, C * h->NTL * 256 * sizeof(float)) == hipSuccess &&
          dmalloc(&h->mu32, C * h->bpad * sizeof(float)) == hipSuccess &&
          dmalloc(&h->mscale, C * sizeof(float)) == hipSuccess &&
+         dmalloc(&h->gredo, C * GRAM_MACROS_MAX * sizeof(int)) == hipSuccess &&
          dmalloc(&h->ctr, 4 * sizeof(unsigned long long)) == hipSuccess;
     if (ok && c.srp_dims > 0) {
         std::vector<float>& W = h->srpW_h;
@@ -354,6 +356,7 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         // 4-band vector loads need b % 4 == 0 and a 4-element aligned buffer
         P.vec4 = (h->wb % 4) == 0 && ((uintptr_t)src % (4 * elem_size(pdt))) == 0;
         P.mscale = h->mscale;
+        P.gredo = h->gredo;
         HIPCHK(run_pass(h->stream, P, h->NT, pdt, c.precision, c.score_arith, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));

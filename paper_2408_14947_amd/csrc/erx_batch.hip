@@ -47,6 +47,7 @@ struct Group {
     float* Mt = nullptr;
     float* mu32 = nullptr;
     float* mscale = nullptr;
+    int* gredo = nullptr;
     int* flags = nullptr;
     float* cond = nullptr;
     StreamDesc* d_sd[NSLOT] = {nullptr, nullptr};
@@ -82,7 +83,7 @@ void destroy_all(erx_batch* bt)
 {
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
     for (auto& g : bt->groups) {
-        void* d[] = {g.stats, g.carry, g.Mt, g.mu32, g.mscale, g.flags, g.cond, g.d_sd[0], g.d_sd[1]};
+        void* d[] = {g.stats, g.carry, g.Mt, g.mu32, g.mscale, g.gredo, g.flags, g.cond, g.d_sd[0], g.d_sd[1]};
         for (void* p : d)
             if (p) (void)hipFree(p);
         for (int k = 0; k < NSLOT; ++k) {
@@ -132,7 +133,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     }
     const erx_config& c = *common;
     if (!(c.ridge >= 0.0f) || !std::isfinite(c.ridge) || (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16) ||
-        c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_FP16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
+        c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1) ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
         c.background != ERX_BG_EMA) {
@@ -187,6 +188,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
              hipMalloc(&g.Mt, C * NTL * 256 * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.mu32, C * 16 * g.NT * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.mscale, C * sizeof(float)) == hipSuccess &&
+             hipMalloc(&g.gredo, C * GRAM_MACROS_MAX * sizeof(int)) == hipSuccess &&
              hipMalloc(&g.flags, C * sizeof(int)) == hipSuccess && hipMalloc(&g.cond, C * sizeof(float)) == hipSuccess;
         for (int k = 0; k < NSLOT && ok; ++k)
             ok = hipMalloc(&g.d_sd[k], ns * sizeof(StreamDesc)) == hipSuccess &&
@@ -375,6 +377,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
             P.pmax = pmax;
             P.vec4 = vec4;
             P.mscale = g.mscale;
+            P.gredo = g.gredo;
             auto record = [&]() -> hipError_t {
                 hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
                                               bt->stream);

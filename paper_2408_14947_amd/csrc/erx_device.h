@@ -37,6 +37,11 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ float absmax4(const f4 v)
+{
+    return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+}
+
 // acc += X^T Y for two accumulator-layout tiles held as register quadruples
 template <class V>
 __device__ __forceinline__ V mma_xty(V acc, const V x, const V y)

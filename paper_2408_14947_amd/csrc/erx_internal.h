@@ -51,7 +51,10 @@ struct Pass {
     int vec4;              // every stream of the pass has a band count divisible by 4
     float* mscale;         // per pass line: max |L^{-1}| (written by the factorisation when
                            // non-null, read by the split-FP16 score kernel)
+    int* gredo;            // per pass line and Gram macro tile (GRAM_MACROS_MAX): 1 when the
+                           // split-FP16 Gram left it to the FP32 pass; null: no split Gram
 };
+constexpr int GRAM_MACROS_MAX = 15;  // upper 64x64 macro tiles of a 304-band Gram
 
 hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s);
 hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s);

@@ -99,7 +99,7 @@ template <int PREC> struct G4;
 template <> struct G4<ERX_GRAM_FP32> {
     static constexpr int WORDS = 64 * 64;  // 32-bit words per panel
     static constexpr int FLUSH = 64;       // pixels per FP32 partial
-    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v)
+    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v, float)
     {
         *(f4*)&T[r * 64 + 4 * (pq ^ g4_sw(r))] = v;
     }
@@ -187,7 +187,7 @@ template <int PREC> struct G4H {
     typedef typename LP<PREC>::v8 v8;
     static constexpr int WORDS = 64 * 32;
     static constexpr int FLUSH = 256;
-    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v)
+    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v, float)
     {
         uint16_t* H = (uint16_t*)T;
         *(v4*)&H[r * 64 + 8 * ((pq >> 1) ^ g4_sw8(r)) + 4 * (pq & 1)] = __builtin_convertvector(v, v4);
@@ -234,14 +234,92 @@ template <int PREC> struct G4H {
 template <> struct G4<ERX_GRAM_BF16> : G4H<ERX_GRAM_BF16> {};
 template <> struct G4<ERX_GRAM_FP16> : G4H<ERX_GRAM_FP16> {};
 
+// Split FP16: x - s, scaled by the band's power of two c (|.| < 2^15), is held as
+// two FP16 halves h = fp16(v c), l = fp16(v c - h) in two planes laid out as the
+// 16-bit rows above; a 32-pixel step of a tile is h_a h_b + h_a l_b + l_a h_b on
+// the 16x16x32 FP16 instruction (products exact in FP32, the dropped l_a l_b
+// below 2^-22 of the product), FP32 partials over 64 pixels.
+template <> struct G4<ERX_GRAM_SPLIT16> {
+    static constexpr int WORDS = 64 * 64;  // hi plane, then lo plane
+    static constexpr int LO = 64 * 64;     // offset of the lo plane in halves
+    static constexpr int FLUSH = 64;
+    static __device__ __forceinline__ void put(uint32_t* T, int r, int pq, const f4 v, float sc)
+    {
+        uint16_t* H = (uint16_t*)T;
+        f4 w4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w4[q] = v[q] * sc;
+        const h4 hi = __builtin_convertvector(w4, h4);
+        const f4 back = __builtin_convertvector(hi, f4);
+        f4 d4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d4[q] = w4[q] - back[q];
+        const int off = r * 64 + 8 * ((pq >> 1) ^ g4_sw8(r)) + 4 * (pq & 1);
+        *(h4*)&H[off] = hi;
+        *(h4*)&H[LO + off] = __builtin_convertvector(d4, h4);
+    }
+    static __device__ __forceinline__ f4 mma(h8 a, h8 b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    template <int NQ>
+    static __device__ __forceinline__ void chunk(const uint32_t* Rt, const uint32_t* Cp, int w, int c, int g,
+                                                 int kend, int qoff, f4* acc)
+    {
+        const uint16_t* RH = (const uint16_t*)Rt;
+        const uint16_t* CH = (const uint16_t*)Cp;
+        const int ra = 16 * w + c;
+        auto rd = [&](int u, h8& ah, h8& al, h8 (&bh)[NQ], h8 (&bl)[NQ]) __attribute__((always_inline)) {
+            const int oc = (u >> 3) + g;
+            const int oa = ra * 64 + 8 * (oc ^ g4_sw8(ra));
+            ah = *(const h8*)&RH[oa];
+            al = *(const h8*)&RH[LO + oa];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int rb = 16 * (q + qoff) + c;
+                const int ob = rb * 64 + 8 * (oc ^ g4_sw8(rb));
+                bh[q] = *(const h8*)&CH[ob];
+                bl[q] = *(const h8*)&CH[LO + ob];
+            }
+        };
+        auto mul = [&](const h8& ah, const h8& al, const h8 (&bh)[NQ], const h8 (&bl)[NQ]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                acc[q] = mma(ah, bh[q], acc[q]);
+                acc[q] = mma(ah, bl[q], acc[q]);
+                acc[q] = mma(al, bh[q], acc[q]);
+            }
+        };
+        // one 32-pixel step's operands at a time (both steps' hi and lo would take 80 registers)
+        for (int u = 0; u < kend; u += 32) {
+            h8 ah, al, bh[NQ], bl[NQ];
+            rd(u, ah, al, bh, bl);
+            mul(ah, al, bh, bl);
+        }
+    }
+};
+
+// power of two c with m c in [2^7, 2^8), so that values up to 128 m stay below
+// 2^15 after scaling (1 when m is 0 or not finite), and 1 / c
+__device__ __forceinline__ void split_scale(float m, float& c, float& inv)
+{
+    int E = ((__float_as_int(m) >> 23) & 0xff) - 127;
+    const bool ok = m > 0.f && E < 128;
+    E = E < -119 ? -119 : (E > 120 ? 120 : E);
+    c = ok ? __int_as_float((127 + 7 - E) << 23) : 1.f;
+    inv = ok ? __int_as_float((127 - 7 + E) << 23) : 1.f;
+}
+
 // The part of a macro tile's work that depends on whether it is diagonal (one
 // panel, rows = columns) is compiled separately for both cases, so that no
 // load sits under a branch.
 template <int DT, int PREC, bool VEC, bool DG>
 __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT, int MI, int MJ, int line,
                                             double* __restrict__ stats, long long E, uint32_t* Rt, uint32_t* Ct,
-                                            float* shift_s, double* red_s, double* bsum_s)
+                                            float* shift_s, double* red_s, double* bsum_s, float* scl_s,
+                                            int* redo_s, int* redo_out)
 {
+    constexpr bool SPLIT = PREC == ERX_GRAM_SPLIT16;
     typedef G4<PREC> G;
     constexpr bool dg = DG;
     const int tid = threadIdx.x;
@@ -323,6 +401,54 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         sr[j] = sc[j] = 0.f;
         dsr[j] = dsc[j] = 0.0;
     }
+    // split FP16: per-band scales from the largest |x - s| of the first chunk
+    // (scl_s: 128 scales, then 128 inverses); a band that is constant over the
+    // first chunk, or a later value beyond the scale's headroom, sends this macro
+    // tile to the FP32 pass (redo)
+    float cr_[4] = {1.f, 1.f, 1.f, 1.f}, cc_[4] = {1.f, 1.f, 1.f, 1.f};
+    bool ovf = false;
+    if constexpr (SPLIT) {
+        const int nv0 = p - 4 * pq;
+        float a[4], e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] = e[j] = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a[j] = fmaxf(a[j], (r < nv0 && rok[j]) ? fabsf(pr[r][j] - shr[j]) : 0.f);
+                if (!dg) e[j] = fmaxf(e[j], (r < nv0 && cok[j]) ? fabsf(pc[r][j] - shc[j]) : 0.f);
+            }
+            if (dg) e[j] = a[j];
+            a[j] = fmaxf(a[j], __shfl_xor(a[j], 16));
+            a[j] = fmaxf(a[j], __shfl_xor(a[j], 32));
+            e[j] = fmaxf(e[j], __shfl_xor(e[j], 16));
+            e[j] = fmaxf(e[j], __shfl_xor(e[j], 32));
+        }
+        float* part = (float*)Rt;  // [4 waves][128 bands], before the first stage
+        if (lane < 16)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                part[w * 128 + 4 * bg + j] = a[j];
+                part[w * 128 + 64 + 4 * bg + j] = e[j];
+            }
+        if (tid == 0) *redo_s = 0;
+        __syncthreads();
+        if (tid < 128) {
+            const float m = fmaxf(fmaxf(part[tid], part[128 + tid]), fmaxf(part[256 + tid], part[384 + tid]));
+            const int band = (tid < 64 ? rb0 : cb0) + (tid & 63);
+            float cs, ci;
+            split_scale(m, cs, ci);
+            scl_s[tid] = cs;
+            scl_s[128 + tid] = ci;
+            if (band < b && !(m > 0.f)) *redo_s = 1;  // constant over the first chunk (or NaN)
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cr_[j] = scl_s[4 * bg + j];
+            cc_[j] = scl_s[64 + 4 * bg + j];
+        }
+    }
     auto stage = [&](int k0, int buf, const f4(&fr)[4], const f4(&fc)[4]) __attribute__((always_inline)) {
         uint32_t* Rb = Rt + buf * G::WORDS;
         uint32_t* Cb = Ct + buf * G::WORDS;
@@ -333,12 +459,16 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = (r < nv && rok[j]) ? fr[r][j] - shr[j] : 0.f;
             sr[j] += (v[0] + v[1]) + (v[2] + v[3]);
-            G::put(Rb, 4 * bg + j, pq, v);
+            if constexpr (SPLIT)
+                ovf = ovf || absmax4(v) * cr_[j] >= 32768.f;
+            G::put(Rb, 4 * bg + j, pq, v, cr_[j]);
             if (!dg) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = (r < nv && cok[j]) ? fc[r][j] - shc[j] : 0.f;
                 sc[j] += (v[0] + v[1]) + (v[2] + v[3]);
-                G::put(Cb, 4 * bg + j, pq, v);
+                if constexpr (SPLIT)
+                    ovf = ovf || absmax4(v) * cc_[j] >= 32768.f;
+                G::put(Cb, 4 * bg + j, pq, v, cc_[j]);
             }
         }
     };
@@ -400,8 +530,16 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         if (((k0 + 64) % G::FLUSH) == 0 || k0 + 64 >= p) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                if constexpr (SPLIT) {
+                    // undo the band scales of row 16w+4g+i and column 16(qoff+q)+c
+                    const double icq = (double)scl_s[128 + 64 + 16 * ((qoff + q) & 3) + c];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) S[q][i] += (double)acc[q][i];
+                    for (int i = 0; i < 4; ++i)
+                        S[q][i] += (double)acc[q][i] * ((double)scl_s[128 + 16 * w + 4 * g + i] * icq);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) S[q][i] += (double)acc[q][i];
+                }
                 acc[q] = f4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
@@ -450,6 +588,12 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
         bsum_s[tid] = (red_s[t] + red_s[128 + t]) + (red_s[256 + t] + red_s[384 + t]);
     }
     __syncthreads();
+    if constexpr (SPLIT) {
+        if (ovf) *redo_s = 1;  // benign race: every writer stores 1
+        __syncthreads();
+        if (tid == 0) *redo_out = *redo_s;
+        if (*redo_s) return;  // uniform: the FP32 pass writes this macro tile
+    }
     if (!rowok) return;
 
     const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
@@ -480,7 +624,7 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
 
 template <int DT, int PREC, bool VEC>
 __global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro, double* __restrict__ stats,
-                                               long long E)
+                                               long long E, const int* __restrict__ only)
 {
     typedef G4<PREC> G;
     const int bid = blockIdx.x;
@@ -500,15 +644,22 @@ __global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro,
         ++MI;
     }
     const int MJ = MI + m;
+    // the FP32 pass after a split-FP16 one recomputes only the macro tiles that one flagged
+    if (only && !glb(only)[(size_t)line * nmacro + (kk - ll * nmacro)]) return;
     __shared__ __attribute__((aligned(16))) uint32_t Rt[2 * G::WORDS];  // two chunk buffers per panel
     __shared__ __attribute__((aligned(16))) uint32_t Ct[2 * G::WORDS];
     __shared__ float shift_s[128];
     __shared__ double red_s[4 * 128];
     __shared__ double bsum_s[128];
+    __shared__ float scl_s[PREC == ERX_GRAM_SPLIT16 ? 256 : 1];
+    __shared__ int redo_s;
+    int* redo_out = P.gredo ? P.gredo + (size_t)line * nmacro + (kk - ll * nmacro) : nullptr;
     if (MI == MJ)
-        gram4_macro<DT, PREC, VEC, true>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s);
+        gram4_macro<DT, PREC, VEC, true>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s, scl_s,
+                                         &redo_s, redo_out);
     else
-        gram4_macro<DT, PREC, VEC, false>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s);
+        gram4_macro<DT, PREC, VEC, false>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s,
+                                          scl_s, &redo_s, redo_out);
 }
 
 // ============================================================================
@@ -1272,21 +1423,21 @@ static int gram_macros(int NT)
 
 template <int PREC, bool VEC>
 static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const Pass& P, int NT, int nm,
-                         double* stats, long long E)
+                         double* stats, long long E, const int* only)
 {
     switch (dtype) {
-    case DT_F32: hipLaunchKernelGGL((k_gram4<DT_F32, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E); break;
-    case DT_F16: hipLaunchKernelGGL((k_gram4<DT_F16, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E); break;
-    default: hipLaunchKernelGGL((k_gram4<DT_U16, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E); break;
+    case DT_F32: hipLaunchKernelGGL((k_gram4<DT_F32, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E, only); break;
+    case DT_F16: hipLaunchKernelGGL((k_gram4<DT_F16, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E, only); break;
+    default: hipLaunchKernelGGL((k_gram4<DT_U16, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E, only); break;
     }
 }
 
 template <int PREC>
 static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const Pass& P, int NT, int nm,
-                         double* stats, long long E)
+                         double* stats, long long E, const int* only = nullptr)
 {
-    if (P.vec4) launch_gram4<PREC, true>(dtype, grid, block, s, P, NT, nm, stats, E);
-    else launch_gram4<PREC, false>(dtype, grid, block, s, P, NT, nm, stats, E);
+    if (P.vec4) launch_gram4<PREC, true>(dtype, grid, block, s, P, NT, nm, stats, E, only);
+    else launch_gram4<PREC, false>(dtype, grid, block, s, P, NT, nm, stats, E, only);
 }
 
 hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s)
@@ -1297,7 +1448,11 @@ hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats
     dim3 grid((unsigned)nblk), block(256);
     if (prec == ERX_GRAM_BF16) launch_gram4<ERX_GRAM_BF16>(dtype, grid, block, s, P, NT, nm, stats, E);
     else if (prec == ERX_GRAM_FP16) launch_gram4<ERX_GRAM_FP16>(dtype, grid, block, s, P, NT, nm, stats, E);
-    else launch_gram4<ERX_GRAM_FP32>(dtype, grid, block, s, P, NT, nm, stats, E);
+    else if (prec == ERX_GRAM_SPLIT16 && P.gredo) {
+        // split FP16, then FP32 for the macro tiles it flagged (the others return at once)
+        launch_gram4<ERX_GRAM_SPLIT16>(dtype, grid, block, s, P, NT, nm, stats, E);
+        launch_gram4<ERX_GRAM_FP32>(dtype, grid, block, s, P, NT, nm, stats, E, P.gredo);
+    } else launch_gram4<ERX_GRAM_FP32>(dtype, grid, block, s, P, NT, nm, stats, E);
     return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Byte offsets of the buffers of one pass of C lines inside the scratch.
 struct Layout {
-    size_t stats, carry, Mt, mu32, mscale, flags, cond, ctr, end;
+    size_t stats, carry, Mt, mu32, mscale, gredo, flags, cond, ctr, end;
 };
 
 Layout layout(int C, int seg, long long E, int NTL, int bpad)
@@ -57,7 +57,8 @@ Layout layout(int C, int seg, long long E, int NTL, int bpad)
     L.Mt = up256(L.carry + nseg * E * sizeof(double));
     L.mu32 = up256(L.Mt + (size_t)C * NTL * 256 * sizeof(float));
     L.mscale = up256(L.mu32 + (size_t)C * bpad * sizeof(float));
-    L.flags = up256(L.mscale + (size_t)C * sizeof(float));
+    L.gredo = up256(L.mscale + (size_t)C * sizeof(float));
+    L.flags = up256(L.gredo + (size_t)C * GRAM_MACROS_MAX * sizeof(int));
     L.cond = up256(L.flags + (size_t)C * sizeof(int));
     L.ctr = up256(L.cond + (size_t)C * sizeof(float));
     L.end = up256(L.ctr + 4 * sizeof(unsigned long long));
@@ -101,7 +102,7 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
     if (!(c.ridge >= 0.0f) || !std::isfinite(c.ridge)) return set_error(ERX_EINVAL, "ridge must be finite and >= 0");
     if (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16)
         return set_error(ERX_EINVAL, "unknown dtype %d", c.dtype);
-    if (c.precision != ERX_GRAM_FP32 && c.precision != ERX_GRAM_BF16 && c.precision != ERX_GRAM_FP16)
+    if (c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16)
         return set_error(ERX_EINVAL, "unknown precision %d", c.precision);
     if (!(c.fp64_cond_threshold >= 0.0)) return set_error(ERX_EINVAL, "fp64_cond_threshold must be >= 0");
     if (c.cond_estimate < -1 || c.cond_estimate > 1) return set_error(ERX_EINVAL, "cond_estimate must be -1, 0 or 1");
@@ -155,6 +156,7 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
     float* Mt = (float*)(base + L.Mt);
     float* mu32 = (float*)(base + L.mu32);
     float* mscale = (float*)(base + L.mscale);
+    int* gredo = (int*)(base + L.gredo);
     int* flags = (int*)(base + L.flags);
     float* cond = (float*)(base + L.cond);
     unsigned long long* ctr = (unsigned long long*)(base + L.ctr);  // counters, not reported here
@@ -194,6 +196,7 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
         P.pmax = c.pixels;
         P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)src % (4 * esz)) == 0;
         P.mscale = mscale;
+        P.gredo = gredo;
         e = run_pass(s, P, NT, c.dtype, c.precision, c.score_arith, stats, carry, Mt, mu32, flags, cond, thr, want_cond, fp64_pass,
                      false, ctr, nullptr);
         if (e != hipSuccess) return set_error(ERX_EDEVICE, "launch failed: %s", hipGetErrorString(e));

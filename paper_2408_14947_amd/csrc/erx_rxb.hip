@@ -121,6 +121,7 @@ struct erx_rxb {
     float* Mt = nullptr;
     float* mu32 = nullptr;
     float* mscale = nullptr;
+    int* gredo = nullptr;
     int* flags = nullptr;
     float* cond = nullptr;
     unsigned long long* ctr = nullptr;
@@ -142,7 +143,7 @@ namespace {
 
 void rxb_free(erx_rxb* r)
 {
-    void* p[] = {r->state, r->stats, r->carry, r->ring, r->fin, r->Mt, r->mu32, r->mscale, r->flags, r->cond,
+    void* p[] = {r->state, r->stats, r->carry, r->ring, r->fin, r->Mt, r->mu32, r->mscale, r->gredo, r->flags, r->cond,
                  r->ctr, r->in[0], r->in[1], r->scores};
     for (void* q : p)
         if (q) (void)hipFree(q);
@@ -176,7 +177,7 @@ erx_rxb* erx_rxb_create(const erx_config* cfg, int window)
     }
     if (c.bands < 1 || c.bands > ERX_MAX_BANDS || c.pixels < 2 || !(c.ridge >= 0.0f) || !std::isfinite(c.ridge) ||
         (c.dtype != ERX_F32 && c.dtype != ERX_F16 && c.dtype != ERX_U16) ||
-        (c.precision != ERX_GRAM_FP32 && c.precision != ERX_GRAM_BF16 && c.precision != ERX_GRAM_FP16) ||
+        c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16 ||
         !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
         c.normalise != 0 || c.cond_estimate < -1 || c.cond_estimate > 1) {
@@ -208,6 +209,7 @@ erx_rxb* erx_rxb_create(const erx_config* cfg, int window)
          hipMalloc(&r->Mt, C * r->NTL * 256 * sizeof(float)) == hipSuccess &&
          hipMalloc(&r->mu32, C * r->bpad * sizeof(float)) == hipSuccess &&
          hipMalloc(&r->mscale, C * sizeof(float)) == hipSuccess &&
+         hipMalloc(&r->gredo, C * GRAM_MACROS_MAX * sizeof(int)) == hipSuccess &&
          hipMalloc(&r->flags, C * sizeof(int)) == hipSuccess && hipMalloc(&r->cond, C * sizeof(float)) == hipSuccess &&
          hipMalloc(&r->ctr, 4 * sizeof(unsigned long long)) == hipSuccess &&
          hipMemset(r->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess &&
@@ -274,6 +276,7 @@ int erx_rxb_push(erx_rxb* r, const void* lines, int n)
         P.seg = seg;
         P.pmax = c.pixels;
         P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)P.one.x % (4 * esz)) == 0;
+        P.gredo = r->gredo;
         RCHK(launch_gram(c.dtype, c.precision, P, r->NT, r->stats, r->stream));
         RCHK(launch_imc_moments(P, r->NT, r->stats, r->stream));
         RCHK(launch_scan_local(P, r->NT, r->stats, r->stream));

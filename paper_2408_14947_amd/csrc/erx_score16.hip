@@ -67,11 +67,6 @@ __device__ __forceinline__ HL split16(const f4 v, float s)
     return r;
 }
 
-__device__ __forceinline__ float absmax4(const f4 v)
-{
-    return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
-}
-
 }  // namespace
 
 template <int NT, int DT, bool VEC>

@@ -168,7 +168,7 @@ int check_args(const erx_config* cfg, int nstreams, erx_tune_result* out)
     if (!cfg || !out) return fail(ERX_EINVAL, "erx_autotune: NULL argument");
     if (nstreams < 1) return fail(ERX_EINVAL, "nstreams must be >= 1, got %d", nstreams);
     if (cfg->bands < 1 || cfg->bands > ERX_MAX_BANDS || cfg->pixels < 2 || cfg->dtype < ERX_F32 ||
-        cfg->dtype > ERX_U16 || cfg->precision < ERX_GRAM_FP32 || cfg->precision > ERX_GRAM_FP16)
+        cfg->dtype > ERX_U16 || cfg->precision < ERX_GRAM_FP32 || cfg->precision > ERX_GRAM_SPLIT16)
         return fail(ERX_EINVAL, "invalid configuration (bands %d, pixels %d, dtype %d, precision %d)", cfg->bands,
                     cfg->pixels, cfg->dtype, cfg->precision);
     return ERX_OK;

@@ -144,3 +144,38 @@ def test_batch_reduced_precision(erx, prec):
         kap = kappa_max(ref)
         log(f"  stream {s} b={b} p={p}: max {rep['max']:.2e} p99 {rep['p99']:.2e} kappa_max {kap:.3g}")
         check(rep, prec, kap)
+
+
+@pytest.mark.parametrize("b,p,T", [(1, 40, 12), (16, 100, 40), (40, 70, 30), (108, 640, 60), (224, 1024, 40),
+                                   (250, 300, 20), (304, 200, 12)])
+def test_split16_gram_parity(erx, b, p, T):
+    """The split-FP16 Gram (FP32-class) stays within the plain path's 1e-4 of the oracle."""
+    log(f"split-FP16 Gram b={b} p={p} T={T}")
+    scene = datagen.make_scene(61, b, b, p, T, drift=True)
+    X, _ = datagen.lines(scene, 0, T)
+    det = erx.Detector(b, p, 0.1, precision="split16", block_lines=16, scan_lines=8)
+    det.push(X.cuda())
+    got = det.scores().cpu().numpy()
+    torch.cuda.synchronize()
+    want = oracle.run(X.numpy(), 0.1, 1e-5)["delta"]
+    err = np.abs(got - want) / np.maximum(want, 1.0)
+    log(f"  max err {err.max():.3e}")
+    assert err.max() <= 1e-4
+
+
+def test_split16_gram_redo_paths(erx):
+    """Blocks the split cannot hold are recomputed in FP32: a band constant over the first
+    64 pixels of a line, and a later pixel 1000 times the first chunk's spread."""
+    log("split-FP16 Gram: FP32 redo of flagged blocks")
+    rng = np.random.default_rng(62)
+    T, p, b = 8, 200, 70
+    X = (0.5 + 0.02 * rng.standard_normal((T, p, b))).astype(np.float32)
+    X[2, :64, 5] = 0.25          # constant over the first chunk of line 2
+    X[5, 150, 40] += 30.0        # far beyond the first chunk's spread in line 5
+    det = erx.Detector(b, p, 0.1, precision="split16")
+    det.push(torch.from_numpy(X).cuda())
+    got = det.scores().cpu().numpy()
+    want = oracle.run(X, 0.1, 1e-5)["delta"]
+    err = np.abs(got - want) / np.maximum(want, 1.0)
+    log(f"  max err {err.max():.3e}")
+    assert err.max() <= 1e-4

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("field,value", [("bands", 0), ("bands", 305), ("pixels", 1),
                                          ("momentum", 0.0), ("momentum", 1.5),
                                          ("momentum", float("nan")), ("ridge", -1e-3),
-                                         ("dtype", 7), ("precision", 3), ("block_lines", 0), ("scan_lines", 0),
+                                         ("dtype", 7), ("precision", 4), ("block_lines", 0), ("scan_lines", 0),
                                          ("warmup", -1), ("fp64_cond_threshold", -1.0),
                                          ("cond_estimate", 2)])
 def test_create_rejects_invalid_config(field, value):
@@ -67,7 +67,7 @@ def test_defaults():
     erx, lib = _lib()
     cfg = erx.Config()
     lib.erx_config_default(C.byref(cfg), 108, 640, 0.1)
-    assert (cfg.bands, cfg.pixels, cfg.dtype, cfg.precision) == (108, 640, 0, 0)
+    assert (cfg.bands, cfg.pixels, cfg.dtype, cfg.precision) == (108, 640, 0, 3)
     assert abs(cfg.ridge - 1e-5) < 1e-12 and cfg.fp64_cond_threshold == 0.0
     assert cfg.block_lines == 2048 and cfg.scan_lines == 64
 
@@ -81,10 +81,10 @@ def test_tune_cache_lookup(tmp_path):
     assert erx.tune_lookup(224, 1024, path) is None  # no file yet
     with open(path, "w") as f:
         f.write('{"erx_tune": 1, "entries": [\n'
-                '  {"bands": 224, "pixels": 1024, "dtype": 0, "precision": 0, "normalise": 0, "nstreams": 1, '
+                '  {"bands": 224, "pixels": 1024, "dtype": 0, "precision": 3, "normalise": 0, "nstreams": 1, '
                 '"fp64_cond_threshold": 0, "block_lines": 4096, "scan_lines": 32, "small_path": -1, '
                 '"us_per_line": 11.5},\n'
-                '  {"bands": 8, "pixels": 1280, "dtype": 1, "precision": 0, "normalise": 0, "nstreams": 1024, '
+                '  {"bands": 8, "pixels": 1280, "dtype": 1, "precision": 3, "normalise": 0, "nstreams": 1024, '
                 '"fp64_cond_threshold": 0, "block_lines": 1024, "scan_lines": 64, "small_path": 1, '
                 '"us_per_line": 0.04}\n]}\n')
     r = erx.tune_lookup(224, 1024, path)
@@ -93,6 +93,7 @@ def test_tune_cache_lookup(tmp_path):
     assert r["small_path"] == 1 and r["block_lines"] == 1024
     assert erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1) is None        # other stream count
     assert erx.tune_lookup(224, 1024, path, precision="bf16") is None             # other precision
+    assert erx.tune_lookup(224, 1024, path, precision="fp32") is None
     assert erx.tune_lookup(224, 1024, path, fp64_cond_threshold=1e6) is None      # other threshold
     with open(path, "w") as f:
         f.write('{"something": "else"}\n')
