@@ -213,8 +213,8 @@ def batched_leg(erx, torch, cfg, T, stream, mixed, n_check):
     stream, each pushed and timed in turn.  Each is timed on its second push of the same
     lines (graphs captured and states warm).  The score error against the FP64 oracle is
     taken on n_check sampled streams (the one with the most bands x pixels included);
-    optionally the mixed configuration (BF16 Gram, FP32 Cholesky with FP64 re-factor above
-    a condition estimate of 1e6) with the same checks."""
+    optionally the mixed configuration (BF16 Gram, FP32 covariance state, FP32 Cholesky with
+    FP64 re-factor above a condition estimate of 1e6) with the same checks."""
     import numpy as np
     import datagen
     scenes = datagen.config_scenes(cfg, scale_lines=T if T > 0 else None)
@@ -306,10 +306,10 @@ def batched_leg(erx, torch, cfg, T, stream, mixed, n_check):
            "err_vs_oracle_worst": {k: max(r[k] for r in per_plain) for k in ("max", "p99", "median")}}
     res["batched"]["hbm_frac"] = res["batched"]["hbm_gbs_in_plus_scores"] / PEAK["hbm_gbs"]
     if mixed:
-        ms_m, got = run_batch(precision="bf16", fp64_cond_threshold=1e6, cond_estimate=1)
+        ms_m, got = run_batch(precision="bf16", fp64_cond_threshold=1e6, cond_estimate=1, state_fp32=True)
         per = check_streams(got)
         del got
-        res["mixed_bf16"] = {"ms": ms_m, "pixels_per_s": n_pix / (ms_m / 1e3), "speedup_vs_batched_plain": ms_b / ms_m,
+        res["mixed_bf16"] = {"config": "BF16 Gram, FP32 state, FP32 Cholesky + FP64 above 1e6", "ms": ms_m, "pixels_per_s": n_pix / (ms_m / 1e3), "speedup_vs_batched_plain": ms_b / ms_m,
                              "err_vs_oracle_per_stream": per,
                              "err_vs_oracle_worst": {k: max(r[k] for r in per) for k in ("max", "p99", "median")},
                              "bound": {"max": MIXED_BOUNDS["bf16"][0], "p99": MIXED_BOUNDS["bf16"][1]}}
@@ -525,8 +525,8 @@ CHECK_ENDS = (32, 5000, 12000, 20000)  # long-scan windows checked against the o
 
 
 def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof, ref_windows):
-    """BF16 / FP16 Gram with FP32 Cholesky (FP64 re-factor above a condition estimate of 1e6)
-    on the same scan: throughput; the score error against the FP64 oracle on the checked
+    """BF16 / FP16 Gram with FP32 covariance state and FP32 Cholesky (FP64 re-factor above a
+    condition estimate of 1e6) on the same scan: throughput; the score error against the FP64 oracle on the checked
     windows (32 lines ending at each of CHECK_ENDS), and against the plain GPU path over
     every pixel of the scan."""
     import numpy as np
@@ -548,7 +548,7 @@ def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof,
         ref = scores()
     res = {"plain_ms_per_step": plain_ms, "plain_gram_ms": plain_prof["gram"][1] / plain_prof["gram"][0]}
     for prec in ("bf16", "fp16"):
-        kw = dict(precision=prec, fp64_cond_threshold=1e6, cond_estimate=1)
+        kw = dict(precision=prec, fp64_cond_threshold=1e6, cond_estimate=1, state_fp32=True)
         ms, _, prof, st = time_workload(erx, torch, X, b, p, momentum, args.steps, args.warmup,
                                         args.block_lines, stream, profile=True, **kw)
         with torch.cuda.stream(stream):

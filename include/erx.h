@@ -113,6 +113,11 @@ typedef struct erx_config {
                           far weighs equally; the background of line t is the mean and the sample
                           covariance (divisor N - 1) of the N = t * pixels pooled pixels (the batch
                           Welford update), plus the ridge; momentum is then unused */
+    int state_fp32;    /* 0 (default): the moving-average state, the per-line statistics and the
+                          scan carries are stored in FP64.  1: they are stored in FP32 (half the
+                          device memory and traffic of the statistics; the averaging recurrence of
+                          Eqs. (20)-(21) is still evaluated in FP64 and each stored value is rounded
+                          once).  erx_get_state / erx_set_state convert; not with ERX_BG_IMC */
 } erx_config;
 
 enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };
@@ -234,7 +239,8 @@ ERX_API int erx_batch_use_graphs(erx_batch *bt, int on);
  * push is at most 40960 bytes and starts on a 16-byte boundary; otherwise each tile is
  * streamed from device memory twice.  mode 1: use it for every such stream; 2: the same
  * but always streamed; 0: never; -1 (default): when at least 32 such streams are in the
- * batch.  Results agree with the general path to rounding.  ERX_EINVAL for another mode. */
+ * batch.  Results agree with the general path to rounding.  A batch made with state_fp32 = 1
+ * never takes it (the fused path keeps an FP64 state).  ERX_EINVAL for another mode. */
 ERX_API int erx_batch_small_path(erx_batch *bt, int mode);
 ERX_API int erx_batch_synchronize(erx_batch *bt);
 ERX_API void erx_batch_destroy(erx_batch *bt);
@@ -341,7 +347,8 @@ ERX_API void erx_surrogate_detector_destroy(erx_sdet *sd);
  * allocating library routine is called; the first call on a device looks up the array's
  * address once (hipGetSymbolAddress), so make one call on each device before capturing.
  *
- *   cfg      as for erx_create_ex; normalise must be 0.  block_lines caps the lines per
+ *   cfg      as for erx_create_ex; normalise, srp_dims and state_fp32 must be 0 and the
+ *            background ERX_BG_EMA.  block_lines caps the lines per
  *            device pass; the scratch caps it further (152 lines at 224 bands, 84 at
  *            304 with scan_lines 64), and longer pushes run in several passes.
  *   state    device buffer of E = 256*NT*(NT+1)/2 + 16*NT doubles, NT = ceil(bands/16): the
@@ -355,7 +362,7 @@ ERX_API void erx_surrogate_detector_destroy(erx_sdet *sd);
  *            enqueued and never waits for the device.
  *
  * Errors: ERX_EINVAL for invalid arguments (bands beyond ERX_MAX_BANDS, the largest size the
- * scratch is laid out for; pixels < 2; n < 1; normalise = 1; a buffer that is not device
+ * scratch is laid out for; pixels < 2; n < 1; normalise = 1; state_fp32 = 1; a buffer that is not device
  * memory ...), with nothing enqueued; ERX_EDEVICE when the scratch address cannot be found
  * or a launch fails.  Lines whose covariance is not positive definite get NaN scores and
  * are not reported (that would need a wait).  Every call on a GPU shares that GPU's scratch
@@ -398,7 +405,8 @@ ERX_API int erx_detection_metrics(const float *scores, const unsigned char *trut
  * the first (window - 1) / 2 lines are never scored, and the last (window - 1) / 2 lines
  * are scored only by later pushes.  cfg: bands, pixels, ridge, dtype, precision,
  * fp64_cond_threshold, cond_estimate, score_arith, block_lines and scan_lines as for
- * erx_create_ex (momentum is unused; srp_dims and normalise must be 0).  window: odd, >= 1.
+ * erx_create_ex (momentum is unused; srp_dims, normalise and state_fp32 must be 0: the window
+ * statistics are differences of running sums, kept in FP64).  window: odd, >= 1.
  * --------------------------------------------------------------------------------------- */
 typedef struct erx_rxb erx_rxb;
 ERX_API erx_rxb *erx_rxb_create(const erx_config *cfg, int window);

@@ -55,7 +55,7 @@ class Config(C.Structure):
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
                 ("cond_estimate", C.c_int), ("score_arith", C.c_int), ("srp_dims", C.c_int),
-                ("srp_seed", C.c_ulonglong), ("background", C.c_int)]
+                ("srp_seed", C.c_ulonglong), ("background", C.c_int), ("state_fp32", C.c_int)]
 
 
 class DetectionMetrics(C.Structure):
@@ -193,10 +193,11 @@ class Detector:
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
                  scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
                  score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0,
-                 background: str = "ema"):
+                 background: str = "ema", state_fp32: bool = False):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
         stream, None = a stream owned by the handle.  srp_dims > 0: project every line
-        to that many dimensions first (Sec. III-B, weights from srp_matrix)."""
+        to that many dimensions first (Sec. III-B, weights from srp_matrix).
+        state_fp32: keep the moving-average state and per-line statistics in FP32."""
         lib = load()
         cfg = Config()
         lib.erx_config_default(C.byref(cfg), int(bands), int(pixels), float(momentum))
@@ -213,6 +214,7 @@ class Detector:
         cfg.srp_dims = int(srp_dims)
         cfg.srp_seed = int(srp_seed)
         cfg.background = BACKGROUNDS[background]
+        cfg.state_fp32 = 1 if state_fp32 else 0
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
         self.work_bands = int(srp_dims) if srp_dims else int(bands)
@@ -337,7 +339,7 @@ class Batch:
                  precision: str = "split16",
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
                  scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True, score_arith: str = "split16",
-                 stream: Optional[int] = -1, small_path: int = -1):
+                 stream: Optional[int] = -1, small_path: int = -1, state_fp32: bool = False):
         lib = load()
         self.bands = [int(x) for x in bands]
         self.pixels = [int(x) for x in pixels]
@@ -355,6 +357,7 @@ class Batch:
         cfg.scan_lines = int(scan_lines)
         cfg.cond_estimate = int(cond_estimate)
         cfg.score_arith = SCORE_ARITH[score_arith]
+        cfg.state_fp32 = 1 if state_fp32 else 0
         b = (C.c_int * ns)(*self.bands)
         p = (C.c_int * ns)(*self.pixels)
         m = (C.c_float * ns)(*[float(x) for x in momentum])

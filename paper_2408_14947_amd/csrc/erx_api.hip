@@ -40,9 +40,11 @@ struct erx_ctx {
     hipStream_t own_stream = nullptr;
     long long t = 0;  // lines absorbed
     // device memory
-    double* state = nullptr;   // [E] background after line t (packed, FP64)
-    double* stats = nullptr;   // [C][E] per-line statistics, then segment-local scan
-    double* carry = nullptr;   // [nseg][E] background entering each scan segment
+    // the three below hold FP64 values, or FP32 ones with cfg.state_fp32 (ss bytes each)
+    void* state = nullptr;     // [E + bpad] background after line t (packed), then (IMC) the reference mean
+    void* stats = nullptr;     // [C][E] per-line statistics, then segment-local scan
+    void* carry = nullptr;     // [nseg][E] background entering each scan segment
+    size_t ss = sizeof(double);
     float* Mt = nullptr;       // [C][NTL][256] inverse-factor tiles
     float* mu32 = nullptr;     // [C][bpad] background mean per line
     float* mscale = nullptr;   // [C] max |L^{-1}| per line (split-FP16 score)
@@ -218,6 +220,14 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "background must be ERX_BG_EMA or ERX_BG_IMC, got %d", c.background);
         return nullptr;
     }
+    if (c.state_fp32 != 0 && c.state_fp32 != 1) {
+        fail(ERX_EINVAL, "state_fp32 must be 0 or 1, got %d", c.state_fp32);
+        return nullptr;
+    }
+    if (c.state_fp32 && c.background == ERX_BG_IMC) {
+        fail(ERX_EINVAL, "state_fp32 = 1 needs background ERX_BG_EMA (the IMC moments are kept in FP64)");
+        return nullptr;
+    }
     if (c.srp_dims < 0 || c.srp_dims > ERX_SRP_MAX_DIMS) {
         fail(ERX_EINVAL, "srp_dims must be 0 (off) or in [1, %d], got %d", ERX_SRP_MAX_DIMS, c.srp_dims);
         return nullptr;
@@ -237,14 +247,15 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
     h->NTL = h->NT * (h->NT + 1) / 2;
     h->bpad = 16 * h->NT;
     h->E = stat_entries(h->NT);
+    h->ss = c.state_fp32 ? sizeof(float) : sizeof(double);
     const size_t C = (size_t)c.block_lines;
     const size_t nseg = (C + c.scan_lines - 1) / c.scan_lines;
     bool ok = hipGetDevice(&h->device) == hipSuccess && hipStreamCreate(&h->own_stream) == hipSuccess;
     h->stream = h->own_stream;
     // the state, then (IMC) the stream's reference mean
-    ok = ok && dmalloc(&h->state, (h->E + h->bpad) * sizeof(double)) == hipSuccess &&
-         dmalloc(&h->stats, C * h->E * sizeof(double)) == hipSuccess &&
-         dmalloc(&h->carry, nseg * h->E * sizeof(double)) == hipSuccess &&
+    ok = ok && dmalloc(&h->state, (h->E + h->bpad) * h->ss) == hipSuccess &&
+         dmalloc(&h->stats, C * h->E * h->ss) == hipSuccess &&
+         dmalloc(&h->carry, nseg * h->E * h->ss) == hipSuccess &&
          dmalloc(&h->Mt, C * h->NTL * 256 * sizeof(float)) == hipSuccess &&
          dmalloc(&h->mu32, C * h->bpad * sizeof(float)) == hipSuccess &&
          dmalloc(&h->mscale, C * sizeof(float)) == hipSuccess &&
@@ -260,7 +271,7 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
              hipMemcpy(h->srpW, W.data(), W.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
              dmalloc(&h->zbuf, C * (size_t)c.pixels * c.srp_dims * sizeof(float)) == hipSuccess;
     }
-    ok = ok && hipMemset(h->state, 0, (h->E + h->bpad) * sizeof(double)) == hipSuccess &&
+    ok = ok && hipMemset(h->state, 0, (h->E + h->bpad) * h->ss) == hipSuccess &&
          hipMemset(h->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
     if (!ok) {
         const hipError_t e = hipGetLastError();
@@ -357,6 +368,7 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.vec4 = (h->wb % 4) == 0 && ((uintptr_t)src % (4 * elem_size(pdt))) == 0;
         P.mscale = h->mscale;
         P.gredo = h->gredo;
+        P.sf32 = c.state_fp32;
         HIPCHK(run_pass(h->stream, P, h->NT, pdt, c.precision, c.score_arith, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));
@@ -426,12 +438,39 @@ int erx_labels(erx_ctx* h, float tau, unsigned char* out)
     return ERX_OK;
 }
 
+// the device state as FP64 values on the host, whatever its storage type
+static hipError_t read_state(erx_ctx* h, std::vector<double>& s)
+{
+    const size_t n = (size_t)(h->E + h->bpad);
+    s.resize(n);
+    if (h->ss == sizeof(double)) {
+        const hipError_t e = hipMemcpyAsync(s.data(), h->state, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        return e == hipSuccess ? hipStreamSynchronize(h->stream) : e;
+    }
+    std::vector<float> f(n);
+    hipError_t e = hipMemcpyAsync(f.data(), h->state, n * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    for (size_t i = 0; i < n; ++i) s[i] = f[i];
+    return e;
+}
+
+static hipError_t write_state(erx_ctx* h, const std::vector<double>& s)
+{
+    hipError_t e;
+    if (h->ss == sizeof(double)) {
+        e = hipMemcpyAsync(h->state, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        return e == hipSuccess ? hipStreamSynchronize(h->stream) : e;
+    }
+    std::vector<float> f(s.begin(), s.end());  // rounded to nearest
+    e = hipMemcpyAsync(h->state, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+    return e == hipSuccess ? hipStreamSynchronize(h->stream) : e;  // f must outlive the copy
+}
+
 int erx_get_state(erx_ctx* h, long long* t, double* mu, double* K)
 {
     if (!h) return fail(ERX_EINVAL, "NULL handle");
-    std::vector<double> s(h->E + h->bpad);
-    HIPCHK(hipMemcpyAsync(s.data(), h->state, s.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<double> s;
+    HIPCHK(read_state(h, s));
     const int b = h->wb, NT = h->NT;
     if (t) *t = h->t;
     std::vector<double> zref;
@@ -478,8 +517,7 @@ int erx_set_state(erx_ctx* h, long long t, const double* mu, const double* K)
                 if ((r >> 4) == (c >> 4)) s[packed_offset(c, r, NT)] = f * K[(size_t)c * b + r];
             }
     }
-    HIPCHK(hipMemcpyAsync(h->state, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(write_state(h, s));
     h->t = t;
     h->have_scores = false;
     return ERX_OK;

@@ -31,7 +31,7 @@ struct BStream {
     int b = 0, p = 0, NT = 0;
     float alpha = 0.f;
     long long t = 0;
-    double* state = nullptr;
+    void* state = nullptr;  // FP64, or FP32 with state_fp32
     float* scores = nullptr;
     float* scores_n = nullptr;
     long long cap_lines = 0;
@@ -42,8 +42,8 @@ struct Group {
     int NT = 0;
     long long E = 0;
     std::vector<int> streams;  // longest work first
-    double* stats = nullptr;
-    double* carry = nullptr;
+    void* stats = nullptr;  // FP64, or FP32 with state_fp32
+    void* carry = nullptr;
     float* Mt = nullptr;
     float* mu32 = nullptr;
     float* mscale = nullptr;
@@ -136,7 +136,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
         c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1) ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
-        c.background != ERX_BG_EMA) {
+        c.background != ERX_BG_EMA || (c.state_fp32 != 0 && c.state_fp32 != 1)) {
         fail(ERX_EINVAL, "erx_batch_create: invalid common configuration");
         return nullptr;
     }
@@ -170,6 +170,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     ok = ok && hipMalloc(&bt->ctr, 4 * sizeof(unsigned long long)) == hipSuccess &&
          hipMemset(bt->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
     const size_t C = (size_t)c.block_lines;
+    const size_t ss = c.state_fp32 ? sizeof(float) : sizeof(double);
     for (auto& kv : byNT) {
         if (!ok) break;
         Group g;
@@ -183,8 +184,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
         const size_t ns = g.streams.size();
         const size_t nseg_max = C / c.scan_lines + ns + 1;
         const size_t NTL = (size_t)g.NT * (g.NT + 1) / 2;
-        ok = ok && hipMalloc(&g.stats, C * g.E * sizeof(double)) == hipSuccess &&
-             hipMalloc(&g.carry, nseg_max * g.E * sizeof(double)) == hipSuccess &&
+        ok = ok && hipMalloc(&g.stats, C * g.E * ss) == hipSuccess &&
+             hipMalloc(&g.carry, nseg_max * g.E * ss) == hipSuccess &&
              hipMalloc(&g.Mt, C * NTL * 256 * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.mu32, C * 16 * g.NT * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.mscale, C * sizeof(float)) == hipSuccess &&
@@ -196,8 +197,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
                  hipEventCreateWithFlags(&g.slot_ev[k], hipEventDisableTiming) == hipSuccess;
         for (int s : g.streams) {
             if (!ok) break;
-            ok = hipMalloc(&bt->st[s].state, g.E * sizeof(double)) == hipSuccess &&
-                 hipMemset(bt->st[s].state, 0, g.E * sizeof(double)) == hipSuccess;
+            ok = hipMalloc(&bt->st[s].state, g.E * ss) == hipSuccess &&
+                 hipMemset(bt->st[s].state, 0, g.E * ss) == hipSuccess;
         }
         bt->groups.push_back(g);
     }
@@ -284,7 +285,9 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
     const int C = c.block_lines, seg = c.scan_lines;
 
     for (Group& g : bt->groups) {
-        if (g.NT == 1 && (bt->small_mode >= 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
+        // (the fused kernels keep an FP64 state: with FP32 storage every group takes the general path)
+        if (g.NT == 1 && !c.state_fp32 &&
+            (bt->small_mode >= 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
             // fused path: one launch, every stream's lines in order
             const int slot = g.next_slot;
             g.next_slot = (g.next_slot + 1) % NSLOT;
@@ -378,6 +381,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
             P.vec4 = vec4;
             P.mscale = g.mscale;
             P.gredo = g.gredo;
+            P.sf32 = c.state_fp32;
             auto record = [&]() -> hipError_t {
                 hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
                                               bt->stream);
@@ -447,8 +451,15 @@ int erx_batch_get_state(erx_batch* bt, int stream, long long* t, double* mu, dou
     const BStream& B = bt->st[stream];
     const long long E = stat_entries(B.NT);
     std::vector<double> s(E);
-    HIPCHK(hipMemcpyAsync(s.data(), B.state, E * sizeof(double), hipMemcpyDeviceToHost, bt->stream));
-    HIPCHK(hipStreamSynchronize(bt->stream));
+    if (bt->cfg.state_fp32) {
+        std::vector<float> f(E);
+        HIPCHK(hipMemcpyAsync(f.data(), B.state, E * sizeof(float), hipMemcpyDeviceToHost, bt->stream));
+        HIPCHK(hipStreamSynchronize(bt->stream));
+        for (long long i = 0; i < E; ++i) s[i] = f[i];
+    } else {
+        HIPCHK(hipMemcpyAsync(s.data(), B.state, E * sizeof(double), hipMemcpyDeviceToHost, bt->stream));
+        HIPCHK(hipStreamSynchronize(bt->stream));
+    }
     const int NTL = B.NT * (B.NT + 1) / 2;
     if (t) *t = B.t;
     if (mu)

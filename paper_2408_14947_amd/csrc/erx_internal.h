@@ -15,8 +15,9 @@ constexpr int MAX_NT = 19;   // 16-band tiles: up to 304 bands
 constexpr int SCORE_PT = 2;  // 16-pixel tiles per wave in the score kernel
 
 // Entries of the packed per-line statistics: the upper triangle of the band
-// covariance as NT(NT+1)/2 tiles of 256 doubles (accumulator layout) followed
-// by the 16*NT mean entries.
+// covariance as NT(NT+1)/2 tiles of 256 values (accumulator layout) followed
+// by the 16*NT mean entries.  The values are FP64, or FP32 in a pass with
+// Pass::sf32 set (statistics, scan carries and the stream's state alike).
 inline long long stat_entries(int NT) { return (long long)NT * (NT + 1) / 2 * 256 + 16LL * NT; }
 
 // One stream's share of a device pass.  A pass processes lines of one or more
@@ -28,7 +29,8 @@ struct StreamDesc {
     const void* x;    // first line of the stream in this pass (device memory)
     float* out;       // scores of that line ([n][p])
     float* outn;      // line-normalised scores, or null
-    double* state;    // moving-average carry of the stream (stat_entries entries)
+    void* state;      // moving-average carry of the stream (stat_entries entries of the
+                      // pass's storage type: double, or float when Pass::sf32 is set)
     long long t0;     // lines the stream had absorbed before this pass
     double alpha;     // momentum
     double eps;       // ridge
@@ -53,18 +55,22 @@ struct Pass {
                            // non-null, read by the split-FP16 score kernel)
     int* gredo;            // per pass line and Gram macro tile (GRAM_MACROS_MAX): 1 when the
                            // split-FP16 Gram left it to the FP32 pass; null: no split Gram
+    int sf32;              // 1: statistics, carries and states are stored in FP32 (the
+                           // averaging itself still runs in FP64); 0: FP64 storage
 };
 constexpr int GRAM_MACROS_MAX = 15;  // upper 64x64 macro tiles of a 304-band Gram
 
-hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s);
-hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s);
+// stats / carry: FP64 or (P.sf32) FP32 arrays of stat_entries(NT) values per line / segment
+hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, void* stats, hipStream_t s);
+hipError_t launch_scan_local(const Pass& P, int NT, void* stats, hipStream_t s);
 // IMC: per-line statistics (K_hat, mu_hat) -> second moments about the stream's reference mean
+// (FP64 storage only)
 hipError_t launch_imc_moments(const Pass& P, int NT, double* stats, hipStream_t s);
-hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s);
+hipError_t launch_scan_carry(const Pass& P, int NT, const void* stats, void* carry, hipStream_t s);
 // fp64 = 1: FP64 factorisation of every line (force = 1) or of the lines the
 // FP32 pass flagged (force = 0).  fp64 = 0: FP32 factorisation; force = 1
 // there means no FP64 pass follows, so a failed pivot marks the line not PD.
-hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,
+hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const void* stats, const void* carry,
                        float* Mt, float* mu32, int* flags, float* cond, double thr, int want_cond,
                        unsigned long long* ctr, hipStream_t s);
 // FP32 scores of every line, or (only != null) of the lines flagged FLAG_SCORE32 in only[]

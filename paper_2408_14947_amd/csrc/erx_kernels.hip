@@ -315,9 +315,9 @@ __device__ __forceinline__ void split_scale(float m, float& c, float& inv)
 // load sits under a branch.
 template <int DT, int PREC, bool VEC, bool DG>
 __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT, int MI, int MJ, int line,
-                                            double* __restrict__ stats, long long E, uint32_t* Rt, uint32_t* Ct,
-                                            float* shift_s, double* red_s, double* bsum_s, float* scl_s,
-                                            int* redo_s, int* redo_out)
+                                            void* __restrict__ stats, int sf32, long long E, uint32_t* Rt,
+                                            uint32_t* Ct, float* shift_s, double* red_s, double* bsum_s,
+                                            float* scl_s, int* redo_s, int* redo_out)
 {
     constexpr bool SPLIT = PREC == ERX_GRAM_SPLIT16;
     typedef G4<PREC> G;
@@ -597,7 +597,8 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
     if (!rowok) return;
 
     const double inv_p = 1.0 / (double)p, inv_p1 = 1.0 / (double)(p - 1);
-    double* ls = stats + (size_t)line * E;
+    double* ls = (double*)stats + (size_t)line * E;
+    float* ls32 = (float*)stats + (size_t)line * E;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (!(tbits & (1 << q))) continue;
@@ -610,20 +611,26 @@ __device__ __forceinline__ void gram4_macro(const void* X, int p, int b, int NT,
             const double srho = bsum_s[16 * rt + 4 * g + i];
             o[i] = (S[q][i] - srho * scol * inv_p) * inv_p1;
         }
-        double* dst = ls + tile_u(4 * MI + rt, 4 * MJ + ct, NT) * 256 + lane * 4;
-        *(double2*)dst = double2{o[0], o[1]};
-        *(double2*)(dst + 2) = double2{o[2], o[3]};
+        const long long off = tile_u(4 * MI + rt, 4 * MJ + ct, NT) * 256 + lane * 4;
+        if (sf32) {
+            *(float4*)(ls32 + off) = float4{(float)o[0], (float)o[1], (float)o[2], (float)o[3]};
+        } else {
+            *(double2*)(ls + off) = double2{o[0], o[1]};
+            *(double2*)(ls + off + 2) = double2{o[2], o[3]};
+        }
     }
     if (dg && g == 0) {
         const long long ntU = (long long)NT * (NT + 1) / 2;
         const int band = 16 * I + c;
-        ls[ntU * 256 + band] = (band < b) ? (double)shift_s[16 * w + c] + bsum_s[16 * w + c] * inv_p : 0.0;
+        const double m = (band < b) ? (double)shift_s[16 * w + c] + bsum_s[16 * w + c] * inv_p : 0.0;
+        if (sf32) ls32[ntU * 256 + band] = (float)m;
+        else ls[ntU * 256 + band] = m;
     }
 }
 
 
 template <int DT, int PREC, bool VEC>
-__global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro, double* __restrict__ stats,
+__global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro, void* __restrict__ stats,
                                                long long E, const int* __restrict__ only)
 {
     typedef G4<PREC> G;
@@ -655,11 +662,11 @@ __global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro,
     __shared__ int redo_s;
     int* redo_out = P.gredo ? P.gredo + (size_t)line * nmacro + (kk - ll * nmacro) : nullptr;
     if (MI == MJ)
-        gram4_macro<DT, PREC, VEC, true>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s, scl_s,
-                                         &redo_s, redo_out);
+        gram4_macro<DT, PREC, VEC, true>(X, p, b, NT, MI, MJ, line, stats, P.sf32, E, Rt, Ct, shift_s, red_s,
+                                         bsum_s, scl_s, &redo_s, redo_out);
     else
-        gram4_macro<DT, PREC, VEC, false>(X, p, b, NT, MI, MJ, line, stats, E, Rt, Ct, shift_s, red_s, bsum_s,
-                                          scl_s, &redo_s, redo_out);
+        gram4_macro<DT, PREC, VEC, false>(X, p, b, NT, MI, MJ, line, stats, P.sf32, E, Rt, Ct, shift_s, red_s,
+                                          bsum_s, scl_s, &redo_s, redo_out);
 }
 
 // ============================================================================
@@ -671,7 +678,8 @@ __global__ __launch_bounds__(256) void k_gram4(const Pass P, int NT, int nmacro,
 // segment; the Cholesky kernel adds D_l * carry, D_l = prod_{segment start..l}
 // (1-a_j), to obtain the full background of line l.
 // ============================================================================
-__global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __restrict__ stats, long long E)
+template <class TS>
+__global__ __launch_bounds__(256) void k_scan_local(const Pass P, TS* __restrict__ stats, long long E)
 {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= E) return;
@@ -680,13 +688,13 @@ __global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __rest
     const int l0 = (gsg - d.seg0) * P.seg;  // stream-local first line
     const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
     const long long t0 = d.t0;
-    double* ptr = stats + (size_t)d.line0 * E + e;
-    double acc = 0.0;
+    TS* ptr = stats + (size_t)d.line0 * E + e;
+    double acc = 0.0;  // the recurrence runs in FP64 whatever the storage type
     int l = l0;
     for (; l + 8 <= l1; l += 8) {
         double v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = ptr[(size_t)(l + q) * E];
+        for (int q = 0; q < 8; ++q) v[q] = (double)ptr[(size_t)(l + q) * E];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const double a = avg_weight(d, t0 + l + q);
@@ -694,12 +702,12 @@ __global__ __launch_bounds__(256) void k_scan_local(const Pass P, double* __rest
             v[q] = acc;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ptr[(size_t)(l + q) * E] = v[q];
+        for (int q = 0; q < 8; ++q) ptr[(size_t)(l + q) * E] = (TS)v[q];
     }
     for (; l < l1; ++l) {
         const double a = avg_weight(d, t0 + l);
-        acc = (1.0 - a) * acc + a * ptr[(size_t)l * E];
-        ptr[(size_t)l * E] = acc;
+        acc = (1.0 - a) * acc + a * (double)ptr[(size_t)l * E];
+        ptr[(size_t)l * E] = (TS)acc;
     }
 }
 
@@ -717,9 +725,10 @@ __global__ __launch_bounds__(256) void k_imc_moments(const Pass P, double* __res
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     const double* mu0 = stats + (size_t)d.line0 * E + ntU * 256;  // the pass's first line of the stream
     const bool fresh = d.t0 == 0;
-    const double* c = fresh ? mu0 : d.state + E;
+    double* state = (double*)d.state;
+    const double* c = fresh ? mu0 : state + E;
     double* ls = stats + (size_t)line * E;
-    if (fresh && line == d.line0 && e < 16 * NT) d.state[E + e] = mu0[e];
+    if (fresh && line == d.line0 && e < 16 * NT) state[E + e] = mu0[e];
     if (e >= ntU * 256) return;
     int u = (int)(e >> 8), I = 0;
     while (u >= NT - I) {
@@ -740,14 +749,15 @@ __device__ __forceinline__ double seg_decay(const StreamDesc& d, long long t0, i
     return P;
 }
 
-__global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* __restrict__ stats,
-                                                    double* __restrict__ carry, long long E)
+template <class TS>
+__global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const TS* __restrict__ stats,
+                                                    TS* __restrict__ carry, long long E)
 {
     const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
     if (e >= E) return;
     const StreamDesc d = P.sd ? load_desc(P.sd + blockIdx.y) : P.one;
-    GLB double* state = glb(d.state);
-    double cv = state[e];
+    GLB TS* state = glb((TS*)d.state);
+    double cv = (double)state[e];
     const int nseg = (d.n + P.seg - 1) / P.seg;
     // decay over a whole segment that does not hold the stream's first line
     // (the same product as seg_decay); other segments take seg_decay
@@ -760,13 +770,13 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
         for (int u = 0; u < U; ++u) {
             const int gs = g0 + u < nseg ? g0 + u : nseg - 1;
             const int l1 = (gs * P.seg + P.seg) < d.n ? (gs * P.seg + P.seg) : d.n;
-            ev[u] = stats[(size_t)(d.line0 + l1 - 1) * E + e];
+            ev[u] = (double)stats[(size_t)(d.line0 + l1 - 1) * E + e];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int gs = g0 + u;
             if (gs < nseg) {
-                carry[(size_t)(d.seg0 + gs) * E + e] = cv;
+                carry[(size_t)(d.seg0 + gs) * E + e] = (TS)cv;
                 const int l0 = gs * P.seg;
                 const int l1 = (l0 + P.seg) < d.n ? (l0 + P.seg) : d.n;
                 const bool whole = l1 - l0 == P.seg && d.t0 + l0 > 0 && d.bg == BG_EMA;
@@ -774,7 +784,7 @@ __global__ __launch_bounds__(256) void k_scan_carry(const Pass P, const double* 
             }
         }
     }
-    state[e] = cv;
+    state[e] = (TS)cv;
 }
 
 // ============================================================================
@@ -806,8 +816,8 @@ template <int NT> struct CholLds {
 };
 
 template <class T, int NT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __restrict__ stats,
-                                                  const double* __restrict__ carry, long long E,
+__global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const void* __restrict__ stats,
+                                                  const void* __restrict__ carry, long long E,
                                                   float* __restrict__ Mt, float* __restrict__ mu32,
                                                   int* __restrict__ flags, float* __restrict__ cond,
                                                   double threshold, int want_cond, int force,
@@ -849,55 +859,58 @@ __global__ __launch_bounds__(NW * 64) void k_chol(const Pass P, const double* __
     // ---- load A_IJ^T = (K_loc + D carry)_{JI} (+ eps on the diagonal)
     V A[SLOTS];
     int tI[SLOTS], tJ[SLOTS];
-    const double* st = stats + (size_t)line * E;
-    const double* cr = carry + (size_t)gseg * E;
     // IMC: the averaged statistics are second moments about the reference mean c
     // (kept after the stream's state); the sample covariance of the N = t p pooled
     // pixels is N / (N - 1) (C - (mu - c)(mu - c)^T)
     const bool imc = sdl.bg == BG_IMC;
-    const double* cref = sdl.state + E;
+    const double* cref = (const double*)sdl.state + E;  // IMC passes store FP64
     const double nfac = imc ? (double)((t0 + lloc + 1) * sdl.p) / (double)((t0 + lloc + 1) * sdl.p - 1) : 1.0;
-    auto mean_at = [&](int q) __attribute__((always_inline)) {
-        return st[(long long)NTL * 256 + q] + D * cr[(long long)NTL * 256 + q];
-    };
+    // the same loads for FP64 and FP32 storage (st, cr: this line's statistics and
+    // its segment's carry); the sums are formed in FP64 either way
+    auto load = [&](const auto* __restrict__ st, const auto* __restrict__ cr) __attribute__((always_inline)) {
+        auto mean_at = [&](int q) __attribute__((always_inline)) {
+            return (double)st[(long long)NTL * 256 + q] + D * (double)cr[(long long)NTL * 256 + q];
+        };
 #pragma unroll
-    for (int j = 0; j < SLOTS; ++j) {
-        const int s = j * NW + w;
-        int I = -1, J = -1;
-        if (s < NTL) {  // scalar decode of the lower-triangle tile index
-            I = 0;
-            while ((I + 1) * (I + 2) / 2 <= s) ++I;
-            J = s - I * (I + 1) / 2;
-        }
-        tI[j] = I;
-        tJ[j] = J;
-        if (I >= 0) {
-            const long long u = tile_u(J, I, NT) * 256;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = rowof<T>(g, i);  // stored in the FP32 accumulator layout
-                const long long o = u + (16 * (row >> 2) + c) * 4 + (row & 3);
-                double v = st[o] + D * cr[o];
-                const int rb = 16 * J + row, cb = 16 * I + c;
-                if (imc && rb < b && cb < b)
-                    v = nfac * (v - (mean_at(rb) - glb(cref)[rb]) * (mean_at(cb) - glb(cref)[cb]));
-                if (rb == cb) v += eps;
-                if (rb >= b || cb >= b) v = (rb == cb) ? 1.0 : 0.0;
-                A[j][i] = (T)v;
+        for (int j = 0; j < SLOTS; ++j) {
+            const int s = j * NW + w;
+            int I = -1, J = -1;
+            if (s < NTL) {  // scalar decode of the lower-triangle tile index
+                I = 0;
+                while ((I + 1) * (I + 2) / 2 <= s) ++I;
+                J = s - I * (I + 1) / 2;
             }
-        } else {
+            tI[j] = I;
+            tJ[j] = J;
+            if (I >= 0) {
+                const long long u = tile_u(J, I, NT) * 256;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) A[j][i] = (T)0;
+                for (int i = 0; i < 4; ++i) {
+                    const int row = rowof<T>(g, i);  // stored in the FP32 accumulator layout
+                    const long long o = u + (16 * (row >> 2) + c) * 4 + (row & 3);
+                    double v = (double)st[o] + D * (double)cr[o];
+                    const int rb = 16 * J + row, cb = 16 * I + c;
+                    if (imc && rb < b && cb < b)
+                        v = nfac * (v - (mean_at(rb) - glb(cref)[rb]) * (mean_at(cb) - glb(cref)[cb]));
+                    if (rb == cb) v += eps;
+                    if (rb >= b || cb >= b) v = (rb == cb) ? 1.0 : 0.0;
+                    A[j][i] = (T)v;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) A[j][i] = (T)0;
+            }
+            __builtin_amdgcn_sched_barrier(0);  // bound the number of loads in flight (registers)
         }
-        __builtin_amdgcn_sched_barrier(0);  // bound the number of loads in flight (registers)
-    }
-    if (!FB || force) {
-        const long long ntU = NTL;
-        for (int q = tid; q < BP; q += NW * 64) {
-            const double v = st[ntU * 256 + q] + D * cr[ntU * 256 + q];
-            mu32[(size_t)line * BP + q] = (q < b) ? (float)v : 0.0f;
+        if (!FB || force) {
+            for (int q = tid; q < BP; q += NW * 64) {
+                const double v = mean_at(q);
+                mu32[(size_t)line * BP + q] = (q < b) ? (float)v : 0.0f;
+            }
         }
-    }
+    };
+    if (P.sf32) load((const float*)stats + (size_t)line * E, (const float*)carry + (size_t)gseg * E);
+    else load((const double*)stats + (size_t)line * E, (const double*)carry + (size_t)gseg * E);
 
     // ---- ||A||_1 (row sums of |A| over the real bands), deterministic
     float anorm = 0.f;
@@ -1423,7 +1436,7 @@ static int gram_macros(int NT)
 
 template <int PREC, bool VEC>
 static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const Pass& P, int NT, int nm,
-                         double* stats, long long E, const int* only)
+                         void* stats, long long E, const int* only)
 {
     switch (dtype) {
     case DT_F32: hipLaunchKernelGGL((k_gram4<DT_F32, PREC, VEC>), grid, block, 0, s, P, NT, nm, stats, E, only); break;
@@ -1434,13 +1447,13 @@ static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const 
 
 template <int PREC>
 static void launch_gram4(int dtype, dim3 grid, dim3 block, hipStream_t s, const Pass& P, int NT, int nm,
-                         double* stats, long long E, const int* only = nullptr)
+                         void* stats, long long E, const int* only = nullptr)
 {
     if (P.vec4) launch_gram4<PREC, true>(dtype, grid, block, s, P, NT, nm, stats, E, only);
     else launch_gram4<PREC, false>(dtype, grid, block, s, P, NT, nm, stats, E, only);
 }
 
-hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats, hipStream_t s)
+hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, void* stats, hipStream_t s)
 {
     const int nm = gram_macros(NT);
     const long long E = stat_entries(NT);
@@ -1456,27 +1469,32 @@ hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, double* stats
     return hipGetLastError();
 }
 
-hipError_t launch_scan_local(const Pass& P, int NT, double* stats, hipStream_t s)
+hipError_t launch_scan_local(const Pass& P, int NT, void* stats, hipStream_t s)
 {
     const long long E = stat_entries(NT);
     dim3 g1((unsigned)((E + 255) / 256), (unsigned)P.nseg);
-    hipLaunchKernelGGL(k_scan_local, g1, dim3(256), 0, s, P, stats, E);
+    if (P.sf32) hipLaunchKernelGGL(k_scan_local<float>, g1, dim3(256), 0, s, P, (float*)stats, E);
+    else hipLaunchKernelGGL(k_scan_local<double>, g1, dim3(256), 0, s, P, (double*)stats, E);
     return hipGetLastError();
 }
 
 hipError_t launch_imc_moments(const Pass& P, int NT, double* stats, hipStream_t s)
 {
+    if (P.sf32) return hipErrorInvalidValue;
     const long long E = stat_entries(NT);
     dim3 g((unsigned)(((long long)NT * (NT + 1) / 2 * 256 + 255) / 256), (unsigned)P.nlines);
     hipLaunchKernelGGL(k_imc_moments, g, dim3(256), 0, s, P, stats, E, NT);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_carry(const Pass& P, int NT, const double* stats, double* carry, hipStream_t s)
+hipError_t launch_scan_carry(const Pass& P, int NT, const void* stats, void* carry, hipStream_t s)
 {
     const long long E = stat_entries(NT);
     dim3 g2((unsigned)((E + 255) / 256), (unsigned)P.nstreams);
-    hipLaunchKernelGGL(k_scan_carry, g2, dim3(256), 0, s, P, stats, carry, E);
+    if (P.sf32)
+        hipLaunchKernelGGL(k_scan_carry<float>, g2, dim3(256), 0, s, P, (const float*)stats, (float*)carry, E);
+    else
+        hipLaunchKernelGGL(k_scan_carry<double>, g2, dim3(256), 0, s, P, (const double*)stats, (double*)carry, E);
     return hipGetLastError();
 }
 
@@ -1486,7 +1504,7 @@ template <class T, int NT> constexpr int chol_waves()
 }
 
 template <class T, int NT>
-static void chol_one(const Pass& P, const double* stats, const double* carry, float* Mt, float* mu32,
+static void chol_one(const Pass& P, const void* stats, const void* carry, float* Mt, float* mu32,
                      int* flags, float* cond, double thr, int want, int force, unsigned long long* ctr,
                      hipStream_t s)
 {
@@ -1497,8 +1515,8 @@ static void chol_one(const Pass& P, const double* stats, const double* carry, fl
 }
 
 template <class T, int... NTs>
-static void chol_dispatch(std::integer_sequence<int, NTs...>, int NT, const Pass& P, const double* stats,
-                          const double* carry, float* Mt, float* mu32, int* flags, float* cond, double thr,
+static void chol_dispatch(std::integer_sequence<int, NTs...>, int NT, const Pass& P, const void* stats,
+                          const void* carry, float* Mt, float* mu32, int* flags, float* cond, double thr,
                           int want, int force, unsigned long long* ctr, hipStream_t s)
 {
     ((NT == NTs + 1 ? chol_one<T, NTs + 1>(P, stats, carry, Mt, mu32, flags, cond, thr, want, force, ctr, s)
@@ -1506,7 +1524,7 @@ static void chol_dispatch(std::integer_sequence<int, NTs...>, int NT, const Pass
      ...);
 }
 
-hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const double* stats, const double* carry,
+hipError_t launch_chol(int fp64, int force, const Pass& P, int NT, const void* stats, const void* carry,
                        float* Mt, float* mu32, int* flags, float* cond, double thr, int want_cond,
                        unsigned long long* ctr, hipStream_t s)
 {

@@ -111,6 +111,7 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
     if (c.normalise != 0) return set_error(ERX_EINVAL, "erx_push_lines_noalloc does not normalise (normalise must be 0)");
     if (c.srp_dims != 0) return set_error(ERX_EINVAL, "erx_push_lines_noalloc keeps every band (srp_dims must be 0)");
     if (c.background != ERX_BG_EMA) return set_error(ERX_EINVAL, "erx_push_lines_noalloc runs the moving averages (background must be ERX_BG_EMA)");
+    if (c.state_fp32 != 0) return set_error(ERX_EINVAL, "erx_push_lines_noalloc keeps an FP64 state (state_fp32 must be 0)");
     if (c.block_lines < 1 || c.scan_lines < 1) return set_error(ERX_EINVAL, "block_lines and scan_lines must be >= 1");
     if (n < 1) return set_error(ERX_EINVAL, "n must be >= 1, got %d", n);
     if (t0 < 0) return set_error(ERX_EINVAL, "t0 must be >= 0");

@@ -43,8 +43,8 @@ struct Profiler {
 // FP64 for every line when thr == 0), scores (split FP16 with an FP32 pass
 // over the lines it flags, or FP32; the split kernel needs P.mscale),
 // optional normalisation.
-hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, int sarith, double* stats,
-                    double* carry, float* Mt,
+hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, int sarith, void* stats,
+                    void* carry, float* Mt,
                     float* mu32, int* flags, float* cond, double thr, int want_cond, bool fp64_pass,
                     bool normalise, unsigned long long* ctr, Profiler* prof);
 

@@ -72,8 +72,8 @@ void Profiler::release()
     pool.clear();
 }
 
-hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, int sarith, double* stats,
-                    double* carry, float* Mt,
+hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, int sarith, void* stats,
+                    void* carry, float* Mt,
                     float* mu32, int* flags, float* cond, double thr, int want_cond, bool fp64_pass,
                     bool normalise, unsigned long long* ctr, Profiler* prof)
 {
@@ -81,7 +81,7 @@ hipError_t run_pass(hipStream_t s, const Pass& P, int NT, int dtype, int prec, i
     hipError_t e;
     if ((e = T(K_GRAM, [&] { return launch_gram(dtype, prec, P, NT, stats, s); })) != hipSuccess) return e;
     if (P.nstreams == 1 && !P.sd && P.one.bg == BG_IMC)
-        if ((e = launch_imc_moments(P, NT, stats, s)) != hipSuccess) return e;
+        if ((e = launch_imc_moments(P, NT, (double*)stats, s)) != hipSuccess) return e;
     if ((e = T(K_SCAN_LOCAL, [&] { return launch_scan_local(P, NT, stats, s); })) != hipSuccess) return e;
     if ((e = T(K_SCAN_CARRY, [&] { return launch_scan_carry(P, NT, stats, carry, s); })) != hipSuccess) return e;
     if (thr > 0.0) {

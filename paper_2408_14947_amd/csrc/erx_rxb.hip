@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_rxb_window(const Pass P, const double* 
         out[e] = 0.0;
         return;
     }
-    const double* cref = d.state + E;  // the moments are taken about this mean
+    const double* cref = (const double*)d.state + E;  // the moments are taken about this mean
     const double mr = wsum(m0 + r) - cref[r], mc = wsum(m0 + c) - cref[c];
     out[e] = wsum(e) - mr * mc;
 }
@@ -180,9 +180,9 @@ erx_rxb* erx_rxb_create(const erx_config* cfg, int window)
         c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16 ||
         !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
-        c.normalise != 0 || c.cond_estimate < -1 || c.cond_estimate > 1) {
+        c.normalise != 0 || c.cond_estimate < -1 || c.cond_estimate > 1 || c.state_fp32 != 0) {
         set_error(ERX_EINVAL, "erx_rxb_create: invalid configuration (bands in [1, %d], pixels >= 2, ridge >= 0, "
-                              "no projection, no normalisation)", ERX_MAX_BANDS);
+                              "no projection, no normalisation, FP64 state)", ERX_MAX_BANDS);
         return nullptr;
     }
     erx_rxb* r = new (std::nothrow) erx_rxb();

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_small(const Pass P, int normalise, unsi
     __shared__ int wn_s[4];
     __shared__ int bad_s;
 
-    GLB double* state = glb(d.state);
+    GLB double* state = glb((double*)d.state);  // the fused path keeps an FP64 state
     double Kst[4] = {0.0, 0.0, 0.0, 0.0}, mst = 0.0;  // wave 0: K (state layout) and mu of band c
     if (w == 0) {
 #pragma unroll
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256, 3) void k_small_l(const Pass P, int normalise,
         }
     };
 
-    GLB double* state = glb(d.state);
+    GLB double* state = glb((double*)d.state);  // the fused path keeps an FP64 state
     double Kst[4] = {0.0, 0.0, 0.0, 0.0}, mst = 0.0;  // wave 0: K (state layout) and mu of band c
     if (w == 0) {
 #pragma unroll

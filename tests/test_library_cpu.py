@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol():
                                          ("momentum", float("nan")), ("ridge", -1e-3),
                                          ("dtype", 7), ("precision", 4), ("block_lines", 0), ("scan_lines", 0),
                                          ("warmup", -1), ("fp64_cond_threshold", -1.0),
-                                         ("cond_estimate", 2)])
+                                         ("cond_estimate", 2), ("state_fp32", 2)])
 def test_create_rejects_invalid_config(field, value):
     erx, lib = _lib()
     cfg = erx.Config()
@@ -70,6 +70,35 @@ def test_defaults():
     assert (cfg.bands, cfg.pixels, cfg.dtype, cfg.precision) == (108, 640, 0, 3)
     assert abs(cfg.ridge - 1e-5) < 1e-12 and cfg.fp64_cond_threshold == 0.0
     assert cfg.block_lines == 2048 and cfg.scan_lines == 64
+    assert (cfg.srp_dims, cfg.background, cfg.state_fp32) == (0, 0, 0)
+
+
+def test_config_layout_matches_the_header():
+    """erx_config_default clears the whole C struct: every byte of the binding's Config
+    (its last field included) is written and nothing after it."""
+    erx, lib = _lib()
+    n = C.sizeof(erx.Config)
+    buf = (C.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
+    lib.erx_config_default(C.cast(buf, C.POINTER(erx.Config)), 8, 16, 0.1)
+    assert all(v == 0xAB for v in buf[n:])
+    cfg = erx.Config.from_buffer_copy(bytes(buf[:n]))
+    assert cfg.state_fp32 == 0 and cfg.bands == 8
+
+
+def test_state_fp32_combinations_rejected():
+    """FP32 storage is for the moving averages: the IMC moments and the RX Baseline's
+    running sums stay FP64, and the allocation-free entry point takes an FP64 state."""
+    erx, lib = _lib()
+    cfg = erx.Config()
+    lib.erx_config_default(C.byref(cfg), 8, 16, 0.1)
+    cfg.state_fp32 = 1
+    cfg.background = 1
+    assert not lib.erx_create_ex(C.byref(cfg)) and "state_fp32" in erx.last_error()
+    cfg.background = 0
+    assert not lib.erx_rxb_create(C.byref(cfg), 5)
+    dummy = C.c_void_p(16)
+    assert lib.erx_push_lines_noalloc(C.byref(cfg), dummy, 0, dummy, 4, dummy, None) == erx.ERX_EINVAL
+    assert "state_fp32" in erx.last_error()
 
 
 def test_tune_cache_lookup(tmp_path):
