@@ -286,9 +286,12 @@ ERX_API int erx_tune_lookup(const erx_config *cfg, int nstreams, const char *cac
  *     z = W x + c (ERX_SURR_K outputs),  u = L_z^{-1} (z - mu_z) with (mu_z, L_z) the ERX
  *     statistics of the z stream (same momentum, first-line initialisation, ridge 1e-5),
  *     o = w2 . relu(A1 u + a1) + c2 (ERX_SURR_HIDDEN hidden units),  score = ||u|| exp(o).
- * Parameters are one flat FP32 vector (the master copy; the projection uses an FP16 copy of
- * W refreshed at every change), laid out as W [K][b] row-major, c [K], A1 [HIDDEN][K]
- * row-major, a1 [HIDDEN], w2 [HIDDEN], c2: erx_surrogate_num_params() floats.
+ * Parameters are one flat FP32 vector (the master copy; every forward pass uses FP16 copies
+ * of the weights W, A1 and w2, refreshed at every change, and the FP32 biases), laid out as
+ * W [K][b] row-major, c [K], A1 [HIDDEN][K] row-major, a1 [HIDDEN], w2 [HIDDEN], c2:
+ * erx_surrogate_num_params() floats.  Scoring lines of at most 1024 pixels is one fused
+ * kernel per call (a workgroup per line; the moving average passes between lines through a
+ * decoupled look-back); longer lines take a staged path with the same results.
  * A handle owns its device memory and its own stream; calls block until done.
  * --------------------------------------------------------------------------------------- */
 #define ERX_SURR_K 16
@@ -301,14 +304,16 @@ ERX_API int erx_surrogate_num_params(const erx_surr *net);
 ERX_API int erx_surrogate_set_params(erx_surr *net, const float *params);
 ERX_API int erx_surrogate_get_params(const erx_surr *net, float *params);
 /* Surrogate scores of n lines [n][pixels][bands] (device FP32) of a stream scored from its
- * first line into out [n][pixels] (device FP32). */
+ * first line into out [n][pixels] (device FP32).  ERX_EDEVICE if a look-back wait of the
+ * fused kernel did not complete (its lines are then NaN). */
 ERX_API int erx_surrogate_scores(erx_surr *net, const float *lines, int n, int pixels, float momentum,
                                  float *out);
 /* One training step on n consecutive lines (device FP32 [n][pixels][bands]) of a stream
  * scored from its first line, against targets [n][pixels] (device FP32, the plain-ERX
  * scores of the same lines): loss = mean (log score - log target)^2 with the z-stream
  * statistics held fixed; the gradient is kept (erx_surrogate_grads) and, for lr > 0, one
- * Adam step (beta 0.9 / 0.999, eps 1e-8) is taken.  *loss receives the loss before the step. */
+ * Adam step (beta 0.9 / 0.999, eps 1e-8) is taken.  *loss receives the loss before the step.
+ * The loss and the gradient are summed in a fixed order: a step is reproducible. */
 ERX_API int erx_surrogate_train_step(erx_surr *net, const float *lines, const float *targets, int n,
                                      int pixels, float momentum, float lr, float *loss);
 /* gradient of the last training step, host array of erx_surrogate_num_params() floats */

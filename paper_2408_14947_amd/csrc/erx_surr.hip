@@ -10,7 +10,15 @@
 // Training minimises mean (log score - log target)^2 over the pixels of a
 // batch of consecutive lines of a stream (scored from its first line), the
 // targets being plain-ERX scores; mu_z and L_z are held fixed in the gradient.
-// Adam with FP32 master weights; the FP16 copy of W is refreshed every step.
+// Adam with FP32 master weights; FP16 copies of the weights (W, A1, w2) are
+// refreshed at every step and used by every forward pass (biases stay FP32).
+// The loss and the gradient are summed in a fixed order (per-workgroup
+// partials, then one ordered reduction), so a step is deterministic.
+//
+// Inference runs as one kernel per call, a workgroup per line: projection,
+// the line's mean and covariance, the moving average through a decoupled
+// look-back over the preceding lines of the launch, the 16x16 factorisation
+// and the network, reading each line once.
 //
 // The surrogate detector scores a stream with the surrogate and checks it:
 // every R-th line is scored twice more, by plain ERX and by the surrogate, both
@@ -30,6 +38,7 @@
 #include <vector>
 
 #include "../../include/erx.h"
+#include "erx_device.h"
 #include "erx_internal.h"
 #include "erx_runtime.h"
 
@@ -74,11 +83,12 @@ __host__ __device__ inline Off offsets(int b)
 template <bool TRAIN>
 __global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, int p, int ngrp,
                                                   const float* __restrict__ Mt, const float* __restrict__ mu32,
-                                                  const float* __restrict__ P, int offA1, int offa1, int offw2,
+                                                  const float* __restrict__ P, const __half* __restrict__ P16,
+                                                  int offA1, int offa1, int offw2,
                                                   int offc2, float* __restrict__ out, const float* __restrict__ target,
                                                   float* __restrict__ U, float* __restrict__ Pre,
                                                   float* __restrict__ G, float* __restrict__ dZ,
-                                                  float* __restrict__ loss, float inv_n)
+                                                  float* __restrict__ lossp, float inv_n)
 {
     __shared__ float Ms[SK * SK];  // M[r][q]
     __shared__ float A1s[SH * SK];
@@ -90,10 +100,10 @@ __global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, i
         const int r = tid >> 4, q = tid & 15;  // Mt holds M^T: element (r, q) of M at lane 16(q/4)+r, reg q%4
         Ms[r * SK + q] = Mt[(size_t)line * 256 + (16 * (q >> 2) + r) * 4 + (q & 3)];
     }
-    for (int i = tid; i < SH * SK; i += 256) A1s[i] = P[offA1 + i];
+    for (int i = tid; i < SH * SK; i += 256) A1s[i] = __half2float(P16[offA1 + i]);
     if (tid < SH) {
         a1s[tid] = P[offa1 + tid];
-        w2s[tid] = P[offw2 + tid];
+        w2s[tid] = __half2float(P16[offw2 + tid]);
     }
     if (tid < SK) mus[tid] = mu32[(size_t)line * SK + tid];
     const float c2 = P[offc2];
@@ -156,21 +166,33 @@ __global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, i
 #pragma unroll
         for (int j = 0; j < SH; ++j) pr[j] = pre[j];
     }
-    // loss: wave sums, then one atomic per workgroup
+    // loss: wave sums, then one partial per workgroup (summed in order by k_sum_ordered)
     float e2 = e * e * inv_n;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) e2 += __shfl_xor(e2, m);
     if ((tid & 63) == 0) red[tid >> 6] = e2;
     __syncthreads();
-    if (tid == 0) atomicAdd(loss, (red[0] + red[1]) + (red[2] + red[3]));
+    if (tid == 0) lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[e] = sum over k of part[k * stride + e], k in order (one thread per entry)
+__global__ __launch_bounds__(256) void k_sum_ordered(const float* __restrict__ part, int nk, long long stride,
+                                                     int n, float* __restrict__ out)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nk; ++k) s += part[(size_t)k * stride + e];
+    out[e] = s;
 }
 
 // Gradient sums over a chunk of pixels, one thread per parameter entry (the
-// parameter layout: W [16][b], c [16], A1 [64][16], a1 [64], w2 [64], c2).
+// parameter layout: W [16][b], c [16], A1 [64][16], a1 [64], w2 [64], c2);
+// chunk k writes its sums to gpart[k][.] for the ordered reduction.
 __global__ __launch_bounds__(256) void k_surr_reduce(const float* __restrict__ X, int b, long long npx, int chunk,
                                                      const float* __restrict__ U, const float* __restrict__ Pre,
                                                      const float* __restrict__ G, const float* __restrict__ dZ,
-                                                     const float* __restrict__ P, float* __restrict__ grad)
+                                                     const __half* __restrict__ P16, float* __restrict__ gpart)
 {
     const Off off = offsets(b);
     const int e = blockIdx.x * 256 + threadIdx.x;
@@ -186,12 +208,12 @@ __global__ __launch_bounds__(256) void k_surr_reduce(const float* __restrict__ X
         for (long long px = p0; px < p1; ++px) s += dZ[px * SK + o];
     } else if (e < off.a1) {  // dA1[j][i] = sum [pre_j > 0] g w2_j u_i
         const int j = (e - off.A1) / SK, i = (e - off.A1) % SK;
-        const float w2j = P[off.w2 + j];
+        const float w2j = __half2float(P16[off.w2 + j]);
         for (long long px = p0; px < p1; ++px)
             s += Pre[px * SH + j] > 0.f ? G[px] * w2j * U[px * SK + i] : 0.f;
     } else if (e < off.w2) {  // da1[j] = sum [pre_j > 0] g w2_j
         const int j = e - off.a1;
-        const float w2j = P[off.w2 + j];
+        const float w2j = __half2float(P16[off.w2 + j]);
         for (long long px = p0; px < p1; ++px) s += Pre[px * SH + j] > 0.f ? G[px] * w2j : 0.f;
     } else if (e < off.c2) {  // dw2[j] = sum g relu(pre_j)
         const int j = e - off.w2;
@@ -199,13 +221,12 @@ __global__ __launch_bounds__(256) void k_surr_reduce(const float* __restrict__ X
     } else {  // dc2 = sum g
         for (long long px = p0; px < p1; ++px) s += G[px];
     }
-    atomicAdd(&grad[e], s);
+    gpart[(size_t)blockIdx.y * off.n + e] = s;
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float* __restrict__ grad,
-                                              float* __restrict__ m, float* __restrict__ v, __half* __restrict__ W16,
-                                              int n, int nW, float lr, float b1, float b2, float eps, float c1,
-                                              float c2)
+                                              float* __restrict__ m, float* __restrict__ v, __half* __restrict__ P16,
+                                              int n, float lr, float b1, float b2, float eps, float c1, float c2)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
@@ -216,13 +237,278 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, const float
     v[e] = vv;
     const float w = P[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
     P[e] = w;
-    if (e < nW) W16[e] = __float2half(w);
+    P16[e] = __float2half(w);
 }
 
-__global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ P, __half* __restrict__ W16, int n)
+__global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ P, __half* __restrict__ P16, int n)
 {
     const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e < n) W16[e] = __float2half(P[e]);
+    if (e < n) P16[e] = __float2half(P[e]);
+}
+
+
+// ---------------------------------------------------------------- fused inference
+// One workgroup per line of the launch, in the order of a ticket taken at its
+// start (so a workgroup only ever waits for workgroups that are already
+// running, which never wait for it):
+//  1. z - zref = W (x - xref) for the line's pixels (FP32 matrix cores, FP16 W),
+//     kept in LDS (band-major, padded rows);
+//  2. the line's mean and covariance (divisor p - 1) of z with FP64 products;
+//  3. the moving average (Eqs. (20)-(21)) as a decoupled look-back (the
+//     single-pass scan of Merrill and Garland, 2016): the workgroup publishes
+//     its aggregate (a_l S_l, decay 1 - a_l), combines the aggregates of the
+//     preceding lines until it meets one whose inclusive value is published
+//     (or the state the previous launch left), and publishes its own inclusive
+//     value C_l = (1 - a_l) C_{l-1} + a_l S_l.  Flags carry the launch's epoch,
+//     so nothing is cleared between launches;
+//  4. L L^T = K_l + eps I in FP64 by one wave, M = L^{-1};
+//  5. per pixel u = M (z - mu_l), the network and the score.
+// A wait that does not end within a bounded number of polls marks the launch
+// failed (err) and the line is scored NaN; every wave always reaches the end.
+constexpr int FP_MAX = 1024;         // pixels of a line the fused kernel holds in LDS
+constexpr int ZS = FP_MAX + 4;       // LDS row of one projected band (padding against bank conflicts)
+constexpr int FW = 8;                // waves per workgroup
+constexpr int SE = SK * SK + SK;     // moving-average state: K row-major [16][16], then mu [16]
+constexpr int SPIN_LIMIT = 1 << 22;  // polls of a look-back flag before the launch is declared failed
+
+template <bool VEC>
+__global__ __launch_bounds__(FW * 64) void k_surr_fused(const float* __restrict__ X, int p, int b, int NTx,
+                                                       const __half* __restrict__ P16,
+                                                       const float* __restrict__ P32, Off off,
+                                                       const float* __restrict__ xref, double alpha, long long t0,
+                                                       double eps, const double* __restrict__ fs_in,
+                                                       double* __restrict__ fs_out,
+                                                       double* __restrict__ lval, double* __restrict__ ldec,
+                                                       unsigned* __restrict__ lflag,
+                                                       unsigned long long* __restrict__ ticket,
+                                                       unsigned long long tbase, unsigned epoch,
+                                                       float* __restrict__ out, int* __restrict__ err)
+{
+    __shared__ f4 Wt[MAX_NT * 64];       // W tiles in operand form (as k_sproj)
+    __shared__ float xr_s[16 * MAX_NT];
+    __shared__ float zs[SK * ZS];        // zs[q * ZS + px]
+    __shared__ double red_s[FW][256];
+    __shared__ double msum_s[32][16];
+    __shared__ double S_s[SE];           // the line's statistics
+    __shared__ double C_s[SE];           // the moving average after the line
+    __shared__ double L_s[SK * 17];
+    __shared__ float M_s[SK * SK], mu_s[SK];
+    __shared__ float A1s[SH * SK], a1s[SH], w2s[SH];
+    __shared__ int line_s, status_s, bad_s;
+
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    constexpr int NTH = FW * 64;
+    if (tid == 0) {
+        line_s = (int)(atomicAdd(ticket, 1ull) - tbase);
+        bad_s = 0;
+    }
+    for (int i = tid; i < NTx * 64; i += NTH) {
+        const int K = i >> 6, l = i & 63, gg = l >> 4, cc = l & 15;
+        f4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int band = 16 * K + 4 * gg + q;
+            v[q] = band < b ? __half2float(P16[off.W + cc * b + band]) : 0.f;
+        }
+        Wt[i] = v;
+    }
+    for (int i = tid; i < 16 * NTx; i += NTH) xr_s[i] = i < b ? xref[i] : 0.f;
+    for (int i = tid; i < SH * SK; i += NTH) A1s[i] = __half2float(P16[off.A1 + i]);
+    if (tid < SH) {
+        a1s[tid] = P32[off.a1 + tid];
+        w2s[tid] = __half2float(P16[off.w2 + tid]);
+    }
+    __syncthreads();
+    const int L = line_s;
+    const float* Xl = X + (size_t)L * p * b;
+
+    // 1. projection of the line into LDS
+    const int ntile = (p + 15) >> 4;
+    for (int tt = w; tt < ntile; tt += FW) {
+        const int px = 16 * tt + c;
+        const bool okp = px < p;
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+        for (int K = 0; K < NTx; ++K) {
+            const int band0 = 16 * K + 4 * g;
+            const bool okl = okp && band0 < b;
+            const f4 v = ldq<DT_F32, VEC>(Xl, okl ? (size_t)px * b + band0 : 0, okl ? b - band0 : 0);
+            f4 r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r[q] = (okl && band0 + q < b) ? v[q] - xr_s[band0 + q] : 0.f;
+            acc = mma_xty(acc, Wt[K * 64 + lane], r);
+        }
+        if (okp) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zs[(4 * g + q) * ZS + px] = acc[q];
+        }
+    }
+    __syncthreads();
+
+    // 2. mean, then the centred covariance from FP64 differences and FP64 products
+    {
+        const int j = tid >> 5, k0 = tid & 31;
+        double sm = 0.0;
+        for (int px = k0; px < p; px += 32) sm += (double)zs[j * ZS + px];
+        msum_s[k0][j] = sm;
+    }
+    __syncthreads();
+    if (tid < SK) {
+        double sm = 0.0;
+        for (int k = 0; k < 32; ++k) sm += msum_s[k][tid];
+        S_s[SK * SK + tid] = sm / (double)p;
+    }
+    __syncthreads();
+    {
+        const double mc = S_s[SK * SK + c];
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        for (int tt = w; tt < ntile; tt += FW) {
+            d4 xv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int px = 16 * tt + 4 * g + i;
+                xv[i] = px < p ? (double)zs[c * ZS + px] - mc : 0.0;
+            }
+            acc = mma_xty(acc, xv, xv);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red_s[w][(4 * i + g) * 16 + c] = acc[i];  // FP64 layout: row 4i+g
+    }
+    __syncthreads();
+    if (tid < SK * SK) {
+        double sm = 0.0;
+#pragma unroll
+        for (int v = 0; v < FW; ++v) sm += red_s[v][tid];
+        S_s[tid] = sm / (double)(p - 1);
+    }
+    __syncthreads();
+
+    // 3. moving average by decoupled look-back
+    const double a = (t0 + L == 0) ? 1.0 : alpha, dL = 1.0 - a;
+    const unsigned fA = 2u * epoch + 1u, fP = 2u * epoch + 2u;
+    if (tid < SE) lval[((size_t)L * 2) * SE + tid] = a * S_s[tid];
+    if (tid == 0) ldec[L] = dL;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&lflag[L], fA, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    double accv = 0.0;  // this thread's entry of the exclusive prefix C_{L-1}
+    if (dL != 0.0) {
+        double accd = 1.0;  // product of the decays of the lines combined so far
+        for (int j = L - 1;; --j) {
+            if (j < 0) {  // the state the previous launch of the stream left
+                if (tid < SE) accv += accd * fs_in[tid];
+                break;
+            }
+            if (tid == 0) {
+                unsigned f = 0;
+                for (int it = 0; it < SPIN_LIMIT; ++it) {
+                    f = __hip_atomic_load(&lflag[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (f >= fA) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                status_s = f == fP ? 2 : (f == fA ? 1 : 0);
+            }
+            __syncthreads();
+            const int st = status_s;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (st == 0) {  // no progress: give up on this line
+                if (tid == 0) {
+                    bad_s = 1;
+                    atomicOr(err, 1);
+                }
+                break;
+            }
+            if (tid < SE) accv += accd * lval[((size_t)j * 2 + (st == 2 ? 1 : 0)) * SE + tid];
+            if (st == 2) break;
+            accd *= ldec[j];
+            __syncthreads();  // status_s is rewritten by the next poll
+            if (accd == 0.0) break;  // the stream's first line: nothing before it counts
+        }
+    }
+    __syncthreads();
+    const bool bad = bad_s != 0;
+    if (tid < SE) {
+        double v = a * S_s[tid];
+        if (dL != 0.0) v += dL * accv;
+        if (bad) v = __builtin_nan("");
+        C_s[tid] = v;
+        lval[((size_t)L * 2 + 1) * SE + tid] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&lflag[L], fP, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // the next launch of the stream starts from here (a second slot: lines of this launch
+    // may still read the state this launch started from)
+    if (L == (int)gridDim.x - 1 && tid < SE) fs_out[tid] = C_s[tid];
+
+    // 4. L L^T = K + eps I: lanes 0..15 of wave 0, lane i owning row i (kept in its own
+    //    row of L_s; values of other rows arrive by shuffles), then M = L^{-1} by columns
+    if (tid < SK) {
+        const int i = tid;
+        double* row = L_s + i * 17;
+#pragma unroll 1
+        for (int k = 0; k < SK; ++k) row[k] = C_s[i * SK + k] + (i == k ? eps : 0.0);
+        bool ok = true;
+#pragma unroll 1
+        for (int k = 0; k < SK; ++k) {
+            const double dkk = __shfl(row[k], k, SK);
+            ok = ok && dkk > 0.0;
+            const double d = sqrt(fmax(dkk, 0.0));
+            const double lik = i > k ? row[k] / d : (i == k ? d : 0.0);
+            row[k] = lik;
+#pragma unroll 1
+            for (int jj = k + 1; jj < SK; ++jj) {
+                const double ljk = __shfl(lik, jj, SK);
+                if (i > k && jj <= i) row[jj] -= lik * ljk;
+            }
+        }
+        if (!ok) bad_s = 1;  // not positive definite
+    }
+    __syncthreads();
+    if (tid < SK) {  // column tid of L^{-1}
+        const int j = tid;
+        double m[SK];
+#pragma unroll
+        for (int ii = 0; ii < SK; ++ii) {
+            double v = ii == j ? 1.0 : 0.0;
+            if (ii > j) {
+#pragma unroll
+                for (int k = 0; k < ii; ++k)
+                    if (k >= j) v -= L_s[ii * 17 + k] * m[k];
+            }
+            m[ii] = ii < j ? 0.0 : v / L_s[ii * 17 + ii];
+        }
+#pragma unroll
+        for (int ii = 0; ii < SK; ++ii) M_s[ii * SK + j] = (float)m[ii];
+        mu_s[tid] = (float)C_s[SK * SK + tid];
+    }
+    __syncthreads();
+
+    // 5. scores: u = M (z - mu), o = w2 . relu(A1 u + a1) + c2, score = ||u|| exp(o)
+    const bool badl = bad_s != 0;
+    const float c2 = P32[off.c2];
+    for (int px = tid; px < p; px += NTH) {
+        float rr[SK];
+#pragma unroll
+        for (int q = 0; q < SK; ++q) rr[q] = zs[q * ZS + px] - mu_s[q];
+        float u[SK], nu2 = 0.f;
+#pragma unroll
+        for (int ii = 0; ii < SK; ++ii) {
+            float sm = 0.f;
+#pragma unroll
+            for (int q = 0; q <= ii; ++q) sm = fmaf(M_s[ii * SK + q], rr[q], sm);
+            u[ii] = sm;
+            nu2 = fmaf(sm, sm, nu2);
+        }
+        float o = c2;
+#pragma unroll 8
+        for (int jj = 0; jj < SH; ++jj) {
+            float sm = a1s[jj];
+#pragma unroll
+            for (int ii = 0; ii < SK; ++ii) sm = fmaf(A1s[jj * SK + ii], u[ii], sm);
+            o = fmaf(w2s[jj], fmaxf(sm, 0.f), o);
+        }
+        out[(size_t)L * p + px] = badl ? __builtin_nanf("") : sqrtf(nu2) * expf(o);
+    }
 }
 
 // ERX workspace of a projected (16-band) stream
@@ -239,9 +525,19 @@ struct Erx16 {
     double* state = nullptr;
     float* xref = nullptr;  // the stream's first pixel
     unsigned long long* ctr = nullptr;
+    // fused inference: two state slots, the look-back values, decays and flags of
+    // the lines of a launch, the ticket counter and the failure flag
+    double* fstate = nullptr;  // [2][SE]
+    double* lval = nullptr;    // [cap][2][SE]
+    double* ldec = nullptr;    // [cap]
+    unsigned* lflag = nullptr; // [cap]
+    unsigned long long* ticket = nullptr;
+    int* err = nullptr;
+    unsigned epoch = 0;             // launches so far (the next launch uses epoch + 1)
+    unsigned long long tickets = 0; // tickets taken so far
     void release()
     {
-        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond, state, xref, ctr};
+        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond, state, xref, ctr, fstate, lval, ldec, lflag, ticket, err};
         for (void* q : d)
             if (q) (void)hipFree(q);
         *this = Erx16();
@@ -252,20 +548,27 @@ struct Erx16 {
             if (hipMalloc(&state, stat_entries(1) * sizeof(double)) != hipSuccess ||
                 hipMalloc(&xref, ERX_MAX_BANDS * sizeof(float)) != hipSuccess ||
                 hipMalloc(&ctr, 4 * sizeof(unsigned long long)) != hipSuccess ||
+                hipMalloc(&fstate, 2 * SE * sizeof(double)) != hipSuccess ||
+                hipMalloc(&ticket, sizeof(unsigned long long)) != hipSuccess ||
+                hipMalloc(&err, sizeof(int)) != hipSuccess ||
                 hipMemset(state, 0, stat_entries(1) * sizeof(double)) != hipSuccess ||
+                hipMemset(fstate, 0, 2 * SE * sizeof(double)) != hipSuccess ||
+                hipMemset(ticket, 0, sizeof(unsigned long long)) != hipSuccess ||
+                hipMemset(err, 0, sizeof(int)) != hipSuccess ||
                 hipMemset(ctr, 0, 4 * sizeof(unsigned long long)) != hipSuccess)
                 return hipErrorOutOfMemory;
         }
         if (n <= cap && p <= capp) return hipSuccess;
         const long long N = std::max(n, cap);
         const int Pp = std::max(p, capp);
-        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond};
+        void* d[] = {Z, stats, carry, Mt, mu32, flags, cond, lval, ldec, lflag};
         for (void* q : d)
             if (q) (void)hipFree(q);
         Z = nullptr;
-        stats = carry = nullptr;
+        stats = carry = lval = ldec = nullptr;
         Mt = mu32 = cond = nullptr;
         flags = nullptr;
+        lflag = nullptr;
         const long long E = stat_entries(1);
         const long long nseg = (N + SEG - 1) / SEG + 2;
         if (hipMalloc(&Z, (size_t)N * Pp * SK * sizeof(float)) != hipSuccess ||
@@ -274,7 +577,11 @@ struct Erx16 {
             hipMalloc(&Mt, (size_t)N * 256 * sizeof(float)) != hipSuccess ||
             hipMalloc(&mu32, (size_t)N * SK * sizeof(float)) != hipSuccess ||
             hipMalloc(&flags, (size_t)N * sizeof(int)) != hipSuccess ||
-            hipMalloc(&cond, (size_t)N * sizeof(float)) != hipSuccess)
+            hipMalloc(&cond, (size_t)N * sizeof(float)) != hipSuccess ||
+            hipMalloc(&lval, (size_t)N * 2 * SE * sizeof(double)) != hipSuccess ||
+            hipMalloc(&ldec, (size_t)N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&lflag, (size_t)N * sizeof(unsigned)) != hipSuccess ||
+            hipMemset(lflag, 0, (size_t)N * sizeof(unsigned)) != hipSuccess)
             return hipErrorOutOfMemory;
         cap = N;
         capp = Pp;
@@ -307,6 +614,37 @@ struct Erx16 {
         if ((e = launch_scan_carry(P, 1, stats, carry, s)) != hipSuccess) return e;
         return launch_chol(1, 1, P, 1, stats, carry, Mt, mu32, flags, cond, 0.0, 0, ctr, s);
     }
+    // the fused kernel over n lines of b bands (p <= FP_MAX): scores into out
+    hipError_t fused(hipStream_t s, const float* X, int n, int p, int b, const __half* P16, const float* P32,
+                     const Off& off, double alpha, long long t0, float* out)
+    {
+        const unsigned ep = epoch + 1;
+        const double* fin = fstate + (size_t)(ep & 1) * SE;
+        double* fout = fstate + (size_t)((ep + 1) & 1) * SE;
+        const int NTx = (b + 15) / 16;
+        const dim3 grid((unsigned)n), block(FW * 64);
+        if (b % 4 == 0 && (uintptr_t)X % 16 == 0)
+            hipLaunchKernelGGL(k_surr_fused<true>, grid, block, 0, s, X, p, b, NTx, P16, P32, off, xref, alpha, t0,
+                               SURR_RIDGE, fin, fout, lval, ldec, lflag, ticket, tickets, ep, out, err);
+        else
+            hipLaunchKernelGGL(k_surr_fused<false>, grid, block, 0, s, X, p, b, NTx, P16, P32, off, xref, alpha, t0,
+                               SURR_RIDGE, fin, fout, lval, ldec, lflag, ticket, tickets, ep, out, err);
+        const hipError_t e = hipGetLastError();
+        if (e == hipSuccess) {
+            epoch = ep;
+            tickets += (unsigned long long)n;
+        }
+        return e;
+    }
+    // the failure flag of the fused launches so far (waits for the stream)
+    hipError_t failed(hipStream_t s, bool* out)
+    {
+        int v = 0;
+        hipError_t e = hipMemcpyAsync(&v, err, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        *out = v != 0;
+        return e;
+    }
 };
 
 bool is_device(const void* ptr)
@@ -328,7 +666,7 @@ struct erx_surr {
     float* grad = nullptr;
     float* m = nullptr;
     float* v = nullptr;
-    __half* W16 = nullptr;
+    __half* P16 = nullptr;  // FP16 copy of every parameter (the kernels read W, A1 and w2 from it)
     float* loss = nullptr;
     long long step = 0;
     hipStream_t stream = nullptr;
@@ -340,6 +678,9 @@ struct erx_surr {
     float* G = nullptr;
     float* dZ = nullptr;
     float* dummy = nullptr;
+    float* lossp = nullptr;  // per-workgroup loss partials
+    float* gpart = nullptr;  // per-chunk gradient partials
+    long long capParts = 0;
 };
 
 struct erx_sdet {
@@ -375,20 +716,31 @@ hipError_t project(erx_surr* net, hipStream_t s, Erx16& erx, const float* X, lon
         const hipError_t e = hipMemcpyAsync(erx.xref, X, net->b * sizeof(float), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
-    return launch_sproj(X, npx, net->b, net->W16, erx.xref, erx.Z, s);
+    return launch_sproj(X, npx, net->b, net->P16, erx.xref, erx.Z, s);
 }
 
+// Surrogate scores of n lines continuing the stream held by erx (t0 lines before).
+// Lines of at most FP_MAX pixels take the fused kernel; longer ones the staged
+// path (projection, the ERX pass on z, the per-pixel network).  A stream keeps
+// one pixel count, so it stays on one path.
 hipError_t net_forward(erx_surr* net, hipStream_t s, Erx16& erx, const float* X, int n, int p, double alpha,
                        long long t0, float* out, float* dummy)
 {
+    if (p <= FP_MAX) {
+        if (t0 == 0) {
+            const hipError_t e = hipMemcpyAsync(erx.xref, X, net->b * sizeof(float), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        return erx.fused(s, X, n, p, net->b, net->P16, net->P, net->off, alpha, t0, out);
+    }
     const long long npx = (long long)n * p;
     hipError_t e = project(net, s, erx, X, npx, t0);
     if (e != hipSuccess) return e;
     if ((e = erx.pass(s, n, p, alpha, t0, dummy)) != hipSuccess) return e;
     const int ngrp = (p + 255) / 256;
     hipLaunchKernelGGL((k_surr_pix<false>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, erx.Z, p, ngrp,
-                       erx.Mt, erx.mu32, net->P, net->off.A1, net->off.a1, net->off.w2, net->off.c2, out, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, nullptr, 0.f);
+                       erx.Mt, erx.mu32, net->P, net->P16, net->off.A1, net->off.a1, net->off.w2, net->off.c2, out,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f);
     return hipGetLastError();
 }
 
@@ -425,15 +777,14 @@ erx_surr* erx_surrogate_create(int bands, unsigned long long seed)
               hipMalloc(&net->P, n * sizeof(float)) == hipSuccess &&
               hipMalloc(&net->grad, n * sizeof(float)) == hipSuccess &&
               hipMalloc(&net->m, n * sizeof(float)) == hipSuccess && hipMalloc(&net->v, n * sizeof(float)) == hipSuccess &&
-              hipMalloc(&net->W16, SK * bands * sizeof(__half)) == hipSuccess &&
+              hipMalloc(&net->P16, n * sizeof(__half)) == hipSuccess &&
               hipMalloc(&net->loss, sizeof(float)) == hipSuccess &&
               hipMemcpy(net->P, h.data(), n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(net->grad, 0, n * sizeof(float)) == hipSuccess &&
               hipMemset(net->m, 0, n * sizeof(float)) == hipSuccess &&
               hipMemset(net->v, 0, n * sizeof(float)) == hipSuccess;
     if (ok) {
-        hipLaunchKernelGGL(k_to_half, dim3((SK * bands + 255) / 256), dim3(256), 0, net->stream, net->P, net->W16,
-                           SK * bands);
+        hipLaunchKernelGGL(k_to_half, dim3((n + 255) / 256), dim3(256), 0, net->stream, net->P, net->P16, n);
         ok = hipStreamSynchronize(net->stream) == hipSuccess;
     }
     if (!ok) {
@@ -449,7 +800,8 @@ void erx_surrogate_destroy(erx_surr* net)
 {
     if (!net) return;
     if (net->stream) (void)hipStreamSynchronize(net->stream);
-    void* d[] = {net->P, net->grad, net->m, net->v, net->W16, net->loss, net->U, net->Pre, net->G, net->dZ, net->dummy};
+    void* d[] = {net->P,  net->grad, net->m,  net->v,     net->P16,   net->loss, net->U,
+                 net->Pre, net->G,    net->dZ, net->dummy, net->lossp, net->gpart};
     for (void* q : d)
         if (q) (void)hipFree(q);
     net->erx.release();
@@ -469,8 +821,8 @@ int erx_surrogate_set_params(erx_surr* net, const float* params)
     HIPCHK(hipMemcpyAsync(net->P, params, net->off.n * sizeof(float), hipMemcpyHostToDevice, net->stream));
     HIPCHK(hipMemsetAsync(net->m, 0, net->off.n * sizeof(float), net->stream));
     HIPCHK(hipMemsetAsync(net->v, 0, net->off.n * sizeof(float), net->stream));
-    hipLaunchKernelGGL(k_to_half, dim3((SK * net->b + 255) / 256), dim3(256), 0, net->stream, net->P, net->W16,
-                       SK * net->b);
+    hipLaunchKernelGGL(k_to_half, dim3((net->off.n + 255) / 256), dim3(256), 0, net->stream, net->P, net->P16,
+                       net->off.n);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(net->stream));
     net->step = 0;
@@ -495,7 +847,9 @@ int erx_surrogate_scores(erx_surr* net, const float* lines, int n, int pixels, f
     if (!net->dummy) HIPCHK(hipMalloc(&net->dummy, (size_t)net->erx.cap * net->erx.capp * sizeof(float)));
     HIPCHK(hipMemsetAsync(net->erx.state, 0, stat_entries(1) * sizeof(double), net->stream));
     HIPCHK(net_forward(net, net->stream, net->erx, lines, n, pixels, momentum, 0, out, net->dummy));
-    HIPCHK(hipStreamSynchronize(net->stream));
+    bool bad = false;
+    HIPCHK(net->erx.failed(net->stream, &bad));
+    if (bad) return fail(ERX_EDEVICE, "erx_surrogate_scores: a look-back wait did not complete");
     return ERX_OK;
 }
 
@@ -530,26 +884,43 @@ int erx_surrogate_train_step(erx_surr* net, const float* lines, const float* tar
     HIPCHK(hipMemsetAsync(net->erx.state, 0, stat_entries(1) * sizeof(double), s));
     HIPCHK(project(net, s, net->erx, lines, N, 0));
     HIPCHK(net->erx.pass(s, n, pixels, momentum, 0, net->dummy));
-    // per-pixel forward and backward, then the gradient sums
-    HIPCHK(hipMemsetAsync(net->loss, 0, sizeof(float), s));
-    HIPCHK(hipMemsetAsync(net->grad, 0, net->off.n * sizeof(float), s));
+    // per-pixel forward and backward, then the gradient sums, each in a fixed order
     const int ngrp = (pixels + 255) / 256;
-    hipLaunchKernelGGL((k_surr_pix<true>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, net->erx.Z,
-                       pixels, ngrp, net->erx.Mt, net->erx.mu32, net->P, net->off.A1, net->off.a1, net->off.w2,
-                       net->off.c2, nullptr, targets, net->U, net->Pre, net->G, net->dZ, net->loss,
-                       (float)(1.0 / (double)N));
-    HIPCHK(hipGetLastError());
+    const long long nblk = (long long)n * ngrp;
     const int chunk = 256;
     const long long nch = (N + chunk - 1) / chunk;
+    const long long parts = std::max<long long>(nblk, nch * net->off.n);
+    if (parts > net->capParts) {
+        if (net->lossp) (void)hipFree(net->lossp);
+        if (net->gpart) (void)hipFree(net->gpart);
+        net->lossp = net->gpart = nullptr;
+        net->capParts = 0;
+        if (hipMalloc(&net->lossp, parts * sizeof(float)) != hipSuccess ||
+            hipMalloc(&net->gpart, parts * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ERX_ENOMEM, "erx_surrogate_train_step: cannot allocate the reduction buffers");
+        }
+        net->capParts = parts;
+    }
+    hipLaunchKernelGGL((k_surr_pix<true>), dim3((unsigned)nblk), dim3(256), 0, s, net->erx.Z, pixels, ngrp,
+                       net->erx.Mt, net->erx.mu32, net->P, net->P16, net->off.A1, net->off.a1, net->off.w2,
+                       net->off.c2, nullptr, targets, net->U, net->Pre, net->G, net->dZ, net->lossp,
+                       (float)(1.0 / (double)N));
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, net->lossp, (int)nblk, 1LL, 1, net->loss);
+    HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_surr_reduce, dim3((unsigned)((net->off.n + 255) / 256), (unsigned)nch), dim3(256), 0, s,
-                       lines, net->b, N, chunk, net->U, net->Pre, net->G, net->dZ, net->P, net->grad);
+                       lines, net->b, N, chunk, net->U, net->Pre, net->G, net->dZ, net->P16, net->gpart);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_ordered, dim3((unsigned)((net->off.n + 255) / 256)), dim3(256), 0, s, net->gpart,
+                       (int)nch, (long long)net->off.n, net->off.n, net->grad);
     HIPCHK(hipGetLastError());
     if (lr > 0.f) {
         ++net->step;
         const float b1 = 0.9f, b2 = 0.999f;
         const float c1 = 1.f - std::pow(b1, (float)net->step), c2 = 1.f - std::pow(b2, (float)net->step);
         hipLaunchKernelGGL(k_adam, dim3((net->off.n + 255) / 256), dim3(256), 0, s, net->P, net->grad, net->m, net->v,
-                           net->W16, net->off.n, SK * net->b, lr, b1, b2, 1e-8f, c1, c2);
+                           net->P16, net->off.n, lr, b1, b2, 1e-8f, c1, c2);
         HIPCHK(hipGetLastError());
     }
     float l = 0.f;
@@ -666,7 +1037,10 @@ int erx_surrogate_detector_push(erx_sdet* sd, const float* lines, int n)
             sd->hs.resize(p);
             sd->hp.resize(p);
             HIPCHK(hipMemcpyAsync(sd->hs.data(), sd->mscore, p * sizeof(float), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            bool bad1 = false, bad2 = false;
+            HIPCHK(sd->erx.failed(s, &bad1));
+            HIPCHK(sd->mon16.failed(s, &bad2));
+            if (bad1 || bad2) return fail(ERX_EDEVICE, "surrogate detector: a look-back wait did not complete");
             const int rc = erx_scores(sd->monitor, sd->hp.data());
             if (rc != ERX_OK && rc != ERX_ENOTPD) return rc;
             std::vector<float> dev(p);
@@ -696,6 +1070,9 @@ int erx_surrogate_detector_scores(erx_sdet* sd, float* out)
 {
     if (!sd || !out) return fail(ERX_EINVAL, "NULL argument");
     if (sd->last_n == 0) return fail(ERX_ESTATE, "no lines pushed yet");
+    bool bad = false;
+    HIPCHK(sd->erx.failed(sd->stream, &bad));
+    if (bad) return fail(ERX_EDEVICE, "surrogate detector: a look-back wait did not complete");
     HIPCHK(hipMemcpyAsync(out, sd->scores, (size_t)sd->last_n * sd->p * sizeof(float), hipMemcpyDefault,
                           sd->stream));
     HIPCHK(hipStreamSynchronize(sd->stream));

@@ -68,3 +68,29 @@ def test_gradients_match_central_differences(name):
         fd = (lp - lm) / (2 * h)
         an = np.asarray(g[name]).reshape(-1)[k]
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (name, k, fd, an)
+
+
+def test_golden_worked_surrogate():
+    """The hand-worked example in tests/golden/surrogate_worked.txt: the projection's
+    orientation, the whitening, the hidden layer (orientation of A1, ReLU, bias), the
+    output layer and the composition score = ||u|| exp(o)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "surrogate_worked.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    s = np.sqrt(31.0 / 2.0)
+    val = {"S": s * np.exp(s - 0.2), "R": s * np.exp(-0.2)}
+    want = np.array([val[r[1]] for r in rows])
+    b = 16
+    X = np.zeros((1, 32, b))
+    for i in range(b):
+        X[0, 2 * i, i] = s
+        X[0, 2 * i + 1, i] = -s
+    P = {"W": np.zeros((S.K, b)), "c": 0.1 * np.arange(1, S.K + 1), "A1": np.zeros((S.HIDDEN, S.K)),
+         "a1": np.zeros(S.HIDDEN), "w2": np.zeros(S.HIDDEN), "c2": np.array([-0.1])}
+    for j in range(S.K):
+        P["W"][j, (j + 1) % b] = 1.0
+    P["A1"][0, 0], P["A1"][1, 0], P["A1"][2, 1] = 1.0, 2.0, -1.0
+    P["a1"][3] = 0.5
+    P["w2"][:4] = [0.5, 0.25, 1.0, -0.2]
+    got = S.forward(P, X, 0.1, ridge=0.0)["score"][0]
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
