@@ -330,15 +330,22 @@ def srp_matrix(bands, d, seed):
     return np.sqrt(s / d) * w
 
 
-def surrogate_leg(erx, torch, stream, steps):
-    """Learned projection surrogate: training on fresh synthetic lines (targets: the plain GPU
-    path), then on held-out streams the error against plain ERX, per-line rank agreement,
-    anomaly AUC and throughput, next to ERX on a sparse random projection (Sec. III-B) and on
-    a dense Gaussian projection to the same 16 dimensions (no network)."""
+def surrogate_leg(erx, torch, stream, train_lines, heldout, heldout_lines):
+    """Learned projection surrogate at the surrogate workload's sizes: training on
+    `train_lines` fresh lines of the 640-pixel mixture generator per band count (64-line
+    streams, targets from the plain GPU path); the drift threshold set from validation
+    streams (1.5 x the largest check drift there); then `heldout` held-out streams of
+    `heldout_lines` lines x 1024 pixels, one at a time: the error against plain ERX (the
+    judge), per-line rank agreement and anomaly AUC for the trained surrogate (unchecked
+    and checked), ERX on a sparse random projection (Sec. III-B) and on a dense Gaussian
+    projection to the same 16 dimensions, each given its best constant correction, and
+    throughput next to plain ERX."""
     import numpy as np
     import datagen
     res = {}
     a = datagen.CONFIGS[5]["momentum"]
+    p_tr, T_tr, p_h = datagen.CONFIGS[5]["pixels"], 64, 1024
+    steps = max(1, train_lines // T_tr)
 
     def ranks(x):
         return torch.argsort(torch.argsort(x, dim=-1), dim=-1).double()
@@ -350,15 +357,11 @@ def surrogate_leg(erx, torch, stream, steps):
         npos, nneg = int(m.sum()), int((~m).sum())
         return float((r[m].sum() - npos * (npos + 1) / 2) / (npos * nneg))
 
-    def compare(got, ref):
-        lr = (torch.log(got.double()) - torch.log(ref.double())).abs().flatten()
-        k = max(1, lr.numel() // 100)
+    def spearman(got, ref):
         rg, rr = ranks(got.double()), ranks(ref.double())
         rg -= rg.mean(-1, keepdim=True)
         rr -= rr.mean(-1, keepdim=True)
-        sp = (rg * rr).sum(-1) / torch.sqrt((rg * rg).sum(-1) * (rr * rr).sum(-1))
-        return {"median_abs_log_ratio": float(lr.median()), "p99_abs_log_ratio": float(torch.topk(lr, k).values.min()),
-                "mean_line_spearman": float(sp.mean())}
+        return float(((rg * rr).sum(-1) / torch.sqrt((rg * rg).sum(-1) * (rr * rr).sum(-1))).mean())
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -369,75 +372,121 @@ def surrogate_leg(erx, torch, stream, steps):
         torch.cuda.synchronize()
         return out, e0.elapsed_time(e1)
 
+    def plain_scores(X):
+        d = erx.Detector(X.shape[2], X.shape[1], a, block_lines=min(X.shape[0], 4096), stream=stream.cuda_stream)
+        out, t = timed(lambda: d.push(X))
+        s_ = d.scores().clone()
+        d.close()
+        return s_, t
+
     for b in (108, 224):
+        print(f"[bench] surrogate b={b}: training on {steps * T_tr} lines", file=sys.stderr, flush=True)
         net = erx.Surrogate(b, seed=b)
-        p_tr, T_tr = 640, 32
+        det = erx.Detector(b, p_tr, a, block_lines=T_tr, stream=stream.cuda_stream)
         losses = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         with torch.cuda.stream(stream):
             for k in range(steps):
                 sc = datagen.make_scene(5, 1000 + k, b, p_tr, T_tr, momentum=a)
                 X = datagen.lines(sc, 0, T_tr, device="cuda")[0]
-                d = erx.Detector(b, p_tr, a, block_lines=T_tr, stream=stream.cuda_stream)
-                d.push(X)
-                tgt = d.scores()
-                lr = 3e-3 if k < steps * 3 // 4 else 1e-3
-                losses.append(net.train_step(X, tgt, a, lr))
-                d.close()
-        # held-out streams
-        Hs, T_h, p_h = 2, 256, 1024
-        rows = {"plain": [], "surrogate": [], "surrogate_unchecked": [], "srp16": [], "gauss16": []}
-        masks, ms = [], {"plain": 0.0, "surrogate": 0.0, "surrogate_unchecked": 0.0}
-        status = []
-        srp = erx.Surrogate(b)
-        gau = erx.Surrogate(b)
+                det.set_state(0)
+                det.push(X)
+                losses.append(net.train_step(X, det.scores(), a, 3e-3 if k < steps * 3 // 4 else 1e-3))
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        det.close()
+        # validation: the drift threshold and the constant corrections of the fixed projections
+        rng = np.random.default_rng(8)
+        s_ = np.sqrt(b)
+        u = rng.random((16, b))
+        fixedW = {"srp16": np.sqrt(s_ / 16) * np.where(u < 1 / (2 * s_), 1.0, np.where(u < 1 / s_, -1.0, 0.0)),
+                  "gauss16": rng.normal(0, 1 / np.sqrt(16), (16, b))}
         base = net.params()
-        for name, W in (("srp", srp_matrix(b, 16, 7)), ("gau", np.random.default_rng(8).normal(0, 1 / np.sqrt(16), (16, b)))):
-            P = {k: np.zeros_like(v) for k, v in base.items()}
-            P["W"] = W
-            P["A1"] = base["A1"]
-            (srp if name == "srp" else gau).set_params(P)
-        for i in range(Hs):
-            sc = datagen.make_scene(5, 90000 + i, b, p_h, T_h, momentum=a)
+        val = []
+        for i in range(4):
             with torch.cuda.stream(stream):
-                X, M = datagen.lines(sc, 0, T_h, device="cuda")
-            torch.cuda.synchronize()
-            det = erx.Detector(b, p_h, a, block_lines=T_h, stream=stream.cuda_stream)
-            det.push(X)  # warm-up of the handle's kernels
-            det.close()
-            det = erx.Detector(b, p_h, a, block_lines=T_h, stream=stream.cuda_stream)
-            _, t = timed(lambda: det.push(X))
-            ms["plain"] += t
-            rows["plain"].append(det.scores())
-            sd = erx.SurrogateDetector(net, p_h, a, drift_threshold=0.05, check_every=32)
-            _, t = timed(lambda: sd.push(X))
-            ms["surrogate"] += t
-            rows["surrogate"].append(sd.scores())
-            status.append(sd.status())
-            net.scores(X[:8], a)  # warm-up
-            su, t = timed(lambda: net.scores(X, a))
-            ms["surrogate_unchecked"] += t
-            rows["surrogate_unchecked"].append(su)
-            rows["srp16"].append(srp.scores(X, a))
-            rows["gauss16"].append(gau.scores(X, a))
-            masks.append(M)
-            det.close()
+                X = datagen.lines(datagen.make_scene(5, 70000 + i, b, p_tr, 512, momentum=a), 0, 512,
+                                  device="cuda")[0]
+            val.append((X, plain_scores(X)[0]))
+        fixed = {}
+        for name, W in fixedW.items():
+            P = {k: np.zeros_like(v) for k, v in base.items()}
+            P["W"], P["A1"] = W, base["A1"]
+            fn = erx.Surrogate(b)
+            fn.set_params(P)
+            lr = torch.cat([(torch.log(fn.scores(X, a).double()) - torch.log(R.double())).flatten() for X, R in val])
+            P["c2"] = np.array([-float(lr.median())])
+            fn.set_params(P)
+            fixed[name] = fn
+        theta = 0.0
+        for X, _ in val:
+            sd = erx.SurrogateDetector(net, p_tr, a, drift_threshold=1e9, check_every=32)
+            sd.push(X)
+            theta = max(theta, 1.5 * sd.drift_stats()["max"])
             sd.close()
-        mask = torch.cat(masks)
-        cat = {k: torch.cat(v) for k, v in rows.items()}
-        npx = Hs * T_h * p_h
-        r = {"train": {"steps": steps, "lines_per_step": T_tr, "pixels": p_tr,
-                       "loss_first10": float(np.mean(losses[:10])), "loss_last10": float(np.mean(losses[-10:]))},
-             "held_out": f"{Hs} streams x {T_h} lines x {p_h} px, seeds disjoint from training",
-             "auc": {k: auc(v, mask) for k, v in cat.items()},
-             "vs_plain": {k: compare(cat[k], cat["plain"])
-                          for k in ("surrogate", "surrogate_unchecked", "srp16", "gauss16")},
-             "pixels_per_s": {"plain": npx / (ms["plain"] / 1e3), "surrogate_checked": npx / (ms["surrogate"] / 1e3),
-                              "surrogate_unchecked": npx / (ms["surrogate_unchecked"] / 1e3)},
-             "detector_status": status}
-        res[f"b{b}"] = r
+        del val
+        # held-out streams, one at a time
+        names = ("surrogate_checked", "surrogate_unchecked", "srp16", "gauss16")
+        lr_s = {k: [] for k in names}
+        sp = {k: [] for k in names}
+        au = {k: [] for k in names + ("plain",)}
+        ms = {"plain": 0.0, "surrogate_checked": 0.0, "surrogate_unchecked": 0.0}
+        status = []
+        net.scores(torch.zeros((2, p_h, b), device="cuda") + 0.5, a)  # warm-up
+        print(f"[bench] surrogate b={b}: {heldout} held-out streams x {heldout_lines} lines", file=sys.stderr,
+              flush=True)
+        for i in range(heldout):
+            with torch.cuda.stream(stream):
+                X, M = datagen.lines(datagen.make_scene(5, 90000 + i, b, p_h, heldout_lines, momentum=a), 0,
+                                     heldout_lines, device="cuda")
+            ref, t = plain_scores(X)
+            ms["plain"] += t
+            got = {}
+            got["surrogate_unchecked"], t = timed(lambda: net.scores(X, a))
+            ms["surrogate_unchecked"] += t
+            sd = erx.SurrogateDetector(net, p_h, a, drift_threshold=theta, check_every=32)
+            _, t = timed(lambda: sd.push(X))
+            ms["surrogate_checked"] += t
+            got["surrogate_checked"] = sd.scores()
+            status.append(sd.status())
+            sd.close()
+            for name, fn in fixed.items():
+                got[name] = fn.scores(X, a)
+            au["plain"].append(auc(ref, M))
+            for k in names:
+                lr = (torch.log(got[k].double()) - torch.log(ref.double())).flatten()
+                lr_s[k].append(lr[::8].float())
+                sp[k].append(spearman(got[k], ref))
+                au[k].append(auc(got[k], M))
+            del X, M, ref, got
+        npx = heldout * heldout_lines * p_h
+        stats = {}
+        for k in names:
+            e = torch.cat(lr_s[k]).double().abs()
+            q = torch.quantile(e[torch.randperm(e.numel(), device=e.device)[:4000000]], 0.99)
+            stats[k] = {"median_abs_log_ratio": float(e.median()), "p99_abs_log_ratio": float(q),
+                        "mean_line_spearman": float(np.mean(sp[k])), "auc_mean": float(np.mean(au[k]))}
+        in_bytes = heldout_lines * p_h * b * 4
+        t_unc = ms["surrogate_unchecked"] / heldout / 1e3
+        res[f"b{b}"] = {
+            "train": {"lines": steps * T_tr, "pixels": p_tr, "lines_per_step": T_tr, "seconds": t_train,
+                      "lines_per_s": steps * T_tr / t_train,
+                      "loss_first10": float(np.mean(losses[:10])), "loss_last50": float(np.mean(losses[-50:]))},
+            "drift_threshold": theta,
+            "held_out": f"{heldout} streams x {heldout_lines} lines x {p_h} px, seeds disjoint from training "
+                        "and validation",
+            "vs_plain": stats, "auc_plain_mean": float(np.mean(au["plain"])),
+            "pixels_per_s": {k: npx / (v / 1e3) for k, v in ms.items()},
+            "fused_inference_hbm_frac": (in_bytes + heldout_lines * p_h * 4) / t_unc / (PEAK["hbm_gbs"] * 1e9),
+            "detector": {"streams_on_surrogate": int(sum(1 for st in status if st["active"])),
+                         "checks": int(sum(st["checks"] for st in status)),
+                         "drifting_checks": int(sum(st["drifts"] for st in status)),
+                         "switched": [st["switched_at"] for st in status if not st["active"]]}}
         net.close()
-        srp.close()
-        gau.close()
+        for fn in fixed.values():
+            fn.close()
+        torch.cuda.empty_cache()
     return res
 
 
@@ -596,7 +645,10 @@ def main():
                     help="lines per stream of the batched-multispectral-f16 measurement (0: the configured 5000)")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the learned-projection surrogate side measurement")
-    ap.add_argument("--surrogate-steps", type=int, default=200, help="training steps per band count")
+    ap.add_argument("--surrogate-train-lines", type=int, default=200000,
+                    help="training lines per band count of the surrogate measurement")
+    ap.add_argument("--surrogate-heldout", type=int, default=32, help="held-out streams of the surrogate measurement")
+    ap.add_argument("--surrogate-heldout-lines", type=int, default=5000, help="lines per held-out stream")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (a known traffic against "
                          "which the FETCH_SIZE / WRITE_SIZE counters are scaled)")
@@ -735,7 +787,8 @@ def main():
 
     if not args.no_surrogate:
         print("[bench] learned projection surrogate", file=sys.stderr, flush=True)
-        out["surrogate"] = surrogate_leg(erx, torch, stream, args.surrogate_steps)
+        out["surrogate"] = surrogate_leg(erx, torch, stream, args.surrogate_train_lines, args.surrogate_heldout,
+                                         args.surrogate_heldout_lines)
 
     if not args.no_cpu_baseline:
         import oracle

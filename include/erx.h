@@ -310,8 +310,10 @@ ERX_API int erx_surrogate_scores(erx_surr *net, const float *lines, int n, int p
                                  float *out);
 /* One training step on n consecutive lines (device FP32 [n][pixels][bands]) of a stream
  * scored from its first line, against targets [n][pixels] (device FP32, the plain-ERX
- * scores of the same lines): loss = mean (log score - log target)^2 with the z-stream
- * statistics held fixed; the gradient is kept (erx_surrogate_grads) and, for lr > 0, one
+ * scores of the same lines): loss = mean w (log score - log target)^2, w = clamp(target^2 /
+ * bands, 1, 100) (a background pixel's squared distance averages the band count, so pixels
+ * plain ERX scores far above the background weigh more), with the z-stream statistics held
+ * fixed; the gradient is kept (erx_surrogate_grads) and, for lr > 0, one
  * Adam step (beta 0.9 / 0.999, eps 1e-8) is taken.  *loss receives the loss before the step.
  * The loss and the gradient are summed in a fixed order: a step is reproducible. */
 ERX_API int erx_surrogate_train_step(erx_surr *net, const float *lines, const float *targets, int n,
@@ -339,6 +341,10 @@ ERX_API int erx_surrogate_detector_scores(erx_sdet *sd, float *out);
  * scored by plain ERX after the switch, or -1 */
 ERX_API int erx_surrogate_detector_status(const erx_sdet *sd, int *active, long long *checks,
                                           long long *drifts, long long *switched_at);
+/* Drift of the last check and the mean and largest drift over all checks so far (a NaN
+ * drift is the largest); ERX_ESTATE before the first check.  Used to set drift_threshold
+ * from the checks of in-distribution streams. */
+ERX_API int erx_surrogate_detector_drift_stats(const erx_sdet *sd, float *last, float *mean, float *max);
 ERX_API void erx_surrogate_detector_destroy(erx_sdet *sd);
 
 /* ---------------------------------------------------------------------------------------

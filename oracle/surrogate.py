@@ -16,8 +16,11 @@ small network corrects the score.
     score  = ||u|| exp(o)
 
 Training loss over the pixels of a batch of lines:
-    mean (log score - log target)^2
-with the targets the plain-ERX scores.  The statistics mu_z and L_z are held
+    mean w (log score - log target)^2,   w = clip(target^2 / b, 1, 100)
+with the targets the plain-ERX scores.  A background pixel's squared distance
+averages b, so w is about 1 there; pixels that plain ERX scores far above the
+background (the anomalies) weigh more, so that the 16 directions are not spent on
+background alone.  The statistics mu_z and L_z are held
 fixed (stop-gradient): gradients flow to W, c, A1, a1, w2 and c2 through u and
 o only.  With W = I (b = 16), c = 0 and w2 = 0 the score is plain ERX.
 
@@ -31,6 +34,7 @@ import numpy as np
 
 K = 16        # projection width
 HIDDEN = 64   # hidden units
+LOSS_WCAP = 100.0  # largest loss weight of a pixel
 
 PARAM_NAMES = ("W", "c", "A1", "a1", "w2", "c2")
 
@@ -91,8 +95,10 @@ def loss_and_grads(params, X, target, momentum: float, ridge: float = 1e-5, stat
     N = n * p
     logs = 0.5 * np.log(f["nu2"]) + f["o"]
     e = logs - np.log(np.asarray(target, np.float64))
-    loss = float((e * e).mean())
-    G = 2.0 * e / N                                   # d loss / d log score   [n, p]
+    b = X.shape[2]
+    w = np.clip(np.asarray(target, np.float64) ** 2 / b, 1.0, LOSS_WCAP)
+    loss = float((w * e * e).mean())
+    G = 2.0 * w * e / N                               # d loss / d log score   [n, p]
     A1 = np.asarray(params["A1"], np.float64)
     w2 = np.asarray(params["w2"], np.float64)
     mask = (f["pre"] > 0.0).astype(np.float64)

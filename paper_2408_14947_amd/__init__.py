@@ -36,7 +36,7 @@ EXPORTS = (
     "erx_surrogate_get_params", "erx_surrogate_scores", "erx_surrogate_train_step",
     "erx_surrogate_grads", "erx_surrogate_destroy", "erx_surrogate_detector_create",
     "erx_surrogate_detector_push", "erx_surrogate_detector_scores", "erx_surrogate_detector_status",
-    "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup", "erx_push_lines_noalloc",
+    "erx_surrogate_detector_drift_stats", "erx_surrogate_detector_destroy", "erx_autotune", "erx_tune_lookup", "erx_push_lines_noalloc",
     "erx_detection_metrics", "erx_srp_matrix", "erx_rxb_create", "erx_rxb_push", "erx_rxb_scores",
     "erx_rxb_destroy",
 )
@@ -133,6 +133,8 @@ def load(path: str = LIB_PATH):
         "erx_surrogate_detector_scores": (ip, [vp, vp]),
         "erx_surrogate_detector_status": (ip, [vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong),
                                                 C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
+        "erx_surrogate_detector_drift_stats": (ip, [vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                                    C.POINTER(C.c_float)]),
         "erx_surrogate_detector_destroy": (None, [vp]),
         "erx_autotune": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
         "erx_tune_lookup": (ip, [C.POINTER(Config), ip, C.c_char_p, C.POINTER(TuneResult)]),
@@ -704,6 +706,12 @@ class SurrogateDetector:
         out = torch.empty((self.last_n, self.pixels), dtype=torch.float32, device="cuda")
         _check(self._lib.erx_surrogate_detector_scores(self._h, C.c_void_p(out.data_ptr())))
         return out
+
+    def drift_stats(self) -> dict:
+        """Drift of the last check and the mean / largest drift over the checks so far."""
+        last, mean, mx = C.c_float(), C.c_float(), C.c_float()
+        _check(self._lib.erx_surrogate_detector_drift_stats(self._h, C.byref(last), C.byref(mean), C.byref(mx)))
+        return dict(last=last.value, mean=mean.value, max=mx.value)
 
     def status(self) -> dict:
         a = C.c_int()

@@ -57,6 +57,7 @@ constexpr int SK = ERX_SURR_K;       // projection width
 constexpr int SH = ERX_SURR_HIDDEN;  // hidden units
 constexpr int SEG = 64;              // scan segment of the projected stream
 constexpr double SURR_RIDGE = 1e-5;  // ridge of the projected stream
+constexpr float LOSS_WCAP = 100.f;   // largest weight of a pixel in the training loss
 
 struct Off {
     int W, c, A1, a1, w2, c2, n;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, i
                                                   int offc2, float* __restrict__ out, const float* __restrict__ target,
                                                   float* __restrict__ U, float* __restrict__ Pre,
                                                   float* __restrict__ G, float* __restrict__ dZ,
-                                                  float* __restrict__ lossp, float inv_n)
+                                                  float* __restrict__ lossp, float inv_n, float inv_b)
 {
     __shared__ float Ms[SK * SK];  // M[r][q]
     __shared__ float A1s[SH * SK];
@@ -138,8 +139,12 @@ __global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, i
         if (ok) out[idx] = sqrtf(nu2) * expf(o);
         return;
     }
-    const float e = ok ? 0.5f * logf(nu2) + o - logf(target[idx]) : 0.f;
-    const float g = 2.f * e * inv_n;
+    // weight of the pixel: its plain-ERX distance squared over the band count (about 1
+    // for background, whose squared distance averages b), clamped to [1, LOSS_WCAP]
+    const float t = ok ? target[idx] : 1.f;
+    const float wt = fminf(LOSS_WCAP, fmaxf(1.f, t * t * inv_b));
+    const float e = ok ? 0.5f * logf(nu2) + o - logf(t) : 0.f;
+    const float g = 2.f * wt * e * inv_n;
     float dU[SK];
 #pragma unroll
     for (int i = 0; i < SK; ++i) dU[i] = g * u[i] / nu2;
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(256) void k_surr_pix(const float* __restrict__ Z, i
         for (int j = 0; j < SH; ++j) pr[j] = pre[j];
     }
     // loss: wave sums, then one partial per workgroup (summed in order by k_sum_ordered)
-    float e2 = e * e * inv_n;
+    float e2 = wt * e * e * inv_n;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) e2 += __shfl_xor(e2, m);
     if ((tid & 63) == 0) red[tid >> 6] = e2;
@@ -294,7 +299,8 @@ __global__ __launch_bounds__(FW * 64) void k_surr_fused(const float* __restrict_
     __shared__ double L_s[SK * 17];
     __shared__ float M_s[SK * SK], mu_s[SK];
     __shared__ float A1s[SH * SK], a1s[SH], w2s[SH];
-    __shared__ int line_s, status_s, bad_s;
+    __shared__ int line_s, status_s, kind_s, bad_s;
+    __shared__ double coef_s[65];
 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
     constexpr int NTH = FW * 64;
@@ -324,18 +330,32 @@ __global__ __launch_bounds__(FW * 64) void k_surr_fused(const float* __restrict_
 
     // 1. projection of the line into LDS
     const int ntile = (p + 15) >> 4;
+    // every band load of a tile is issued before its products, so that each wave keeps
+    // up to MAX_NT loads in flight (one workgroup per CU: the loads in flight set the
+    // bandwidth)
     for (int tt = w; tt < ntile; tt += FW) {
         const int px = 16 * tt + c;
         const bool okp = px < p;
-        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-        for (int K = 0; K < NTx; ++K) {
-            const int band0 = 16 * K + 4 * g;
-            const bool okl = okp && band0 < b;
-            const f4 v = ldq<DT_F32, VEC>(Xl, okl ? (size_t)px * b + band0 : 0, okl ? b - band0 : 0);
-            f4 r;
+        f4 v[MAX_NT];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) r[q] = (okl && band0 + q < b) ? v[q] - xr_s[band0 + q] : 0.f;
-            acc = mma_xty(acc, Wt[K * 64 + lane], r);
+        for (int K = 0; K < MAX_NT; ++K) {
+            if (K < NTx) {
+                const int band0 = 16 * K + 4 * g;
+                const bool okl = okp && band0 < b;
+                v[K] = ldq<DT_F32, VEC>(Xl, okl ? (size_t)px * b + band0 : 0, okl ? b - band0 : 0);
+            }
+        }
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int K = 0; K < MAX_NT; ++K) {
+            if (K < NTx) {
+                const int band0 = 16 * K + 4 * g;
+                const bool okl = okp && band0 < b;
+                f4 r;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = (okl && band0 + q < b) ? v[K][q] - xr_s[band0 + q] : 0.f;
+                acc = mma_xty(acc, Wt[K * 64 + lane], r);
+            }
         }
         if (okp) {
 #pragma unroll
@@ -385,43 +405,87 @@ __global__ __launch_bounds__(FW * 64) void k_surr_fused(const float* __restrict_
     // 3. moving average by decoupled look-back
     const double a = (t0 + L == 0) ? 1.0 : alpha, dL = 1.0 - a;
     const unsigned fA = 2u * epoch + 1u, fP = 2u * epoch + 2u;
+    // publication: the barrier completes every wave's stores to the (per-XCD) L2, then one
+    // agent-scope release by the flag's writer makes them visible device-wide
     if (tid < SE) lval[((size_t)L * 2) * SE + tid] = a * S_s[tid];
     if (tid == 0) ldec[L] = dL;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) __hip_atomic_store(&lflag[L], fA, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     double accv = 0.0;  // this thread's entry of the exclusive prefix C_{L-1}
     if (dL != 0.0) {
-        double accd = 1.0;  // product of the decays of the lines combined so far
-        for (int j = L - 1;; --j) {
-            if (j < 0) {  // the state the previous launch of the stream left
-                if (tid < SE) accv += accd * fs_in[tid];
-                break;
-            }
-            if (tid == 0) {
-                unsigned f = 0;
-                for (int it = 0; it < SPIN_LIMIT; ++it) {
-                    f = __hip_atomic_load(&lflag[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    if (f >= fA) break;
-                    __builtin_amdgcn_s_sleep(1);
+        // Windows of 64 preceding lines, newest first: wave 0 polls their flags at once
+        // (lane k the line j0 - k) until each holds at least an aggregate, and finds the
+        // newest line whose inclusive value is published (or the start of the launch);
+        // then every thread folds the aggregates before it into its entry.
+        double accd = 1.0;  // product of the decays of the lines folded so far
+        int j0 = L - 1;
+        for (;;) {
+            if (w == 0) {
+                const int j = j0 - lane;
+                int st = 3;  // before the launch: the state the previous launch left
+                if (j >= 0) {
+                    unsigned f = 0;
+                    for (int it = 0; it < SPIN_LIMIT; ++it) {
+                        f = __hip_atomic_load(&lflag[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (f >= fA) break;
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    st = f == fP ? 2 : (f == fA ? 1 : 0);
                 }
-                status_s = f == fP ? 2 : (f == fA ? 1 : 0);
+                // one acquire for the flags just read: the values they publish (and, through
+                // the CU's caches, the whole workgroup's later loads) are current
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const unsigned long long stop = __ballot(st >= 2), lost = __ballot(st == 0);
+                const int d = stop ? __builtin_ctzll(stop) : 64;  // aggregates to fold first
+                const bool lostw = (lost & (d == 64 ? ~0ull : ((1ull << d) - 1))) != 0;
+                // coefficient of lane k's term: accd times the decays of the newer lines of
+                // the window (an exclusive prefix product over the lanes)
+                double dk = (lane < d && st == 1) ? ldec[j] : 1.0;
+                double incl = dk;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const double o = __shfl_up(incl, off);
+                    if (lane >= off) incl *= o;
+                }
+                double excl = __shfl_up(incl, 1);
+                if (lane == 0) excl = 1.0;
+                coef_s[lane] = accd * excl;
+                if (lane == 63) coef_s[64] = accd * incl;
+                if (lane == 0) status_s = lostw ? 0 : 1 + 4 * d;  // 0: failed, else 1 + 4 d
+                if (lane == (d < 64 ? d : 0)) kind_s = d < 64 ? st : 1;  // what ends the window
             }
             __syncthreads();
-            const int st = status_s;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (st == 0) {  // no progress: give up on this line
+            const int code = status_s, kind = kind_s;
+            if (code == 0) {  // no progress: give up on this line
                 if (tid == 0) {
                     bad_s = 1;
                     atomicOr(err, 1);
                 }
                 break;
             }
-            if (tid < SE) accv += accd * lval[((size_t)j * 2 + (st == 2 ? 1 : 0)) * SE + tid];
-            if (st == 2) break;
-            accd *= ldec[j];
-            __syncthreads();  // status_s is rewritten by the next poll
-            if (accd == 0.0) break;  // the stream's first line: nothing before it counts
+            const int d = (code - 1) >> 2;
+            if (tid < SE) {
+                double sacc = 0.0;
+#pragma unroll 8
+                for (int k = 0; k < d; ++k) {
+                    const double cf = coef_s[k];
+                    const double v = lval[((size_t)(j0 - k) * 2) * SE + tid];
+                    sacc += cf != 0.0 ? cf * v : 0.0;  // a zero coefficient: lines before the stream's first
+                }
+                if (d < 64) {
+                    const double cf = coef_s[d];
+                    if (cf != 0.0) {
+                        if (kind == 2) sacc += cf * lval[((size_t)(j0 - d) * 2 + 1) * SE + tid];
+                        else sacc += cf * fs_in[tid];
+                    }
+                }
+                accv += sacc;
+            }
+            accd = coef_s[64];
+            const bool done = d < 64 || accd == 0.0;
+            __syncthreads();  // the window's shared values are rewritten by the next one
+            if (done) break;
+            j0 -= 64;
         }
     }
     __syncthreads();
@@ -433,7 +497,6 @@ __global__ __launch_bounds__(FW * 64) void k_surr_fused(const float* __restrict_
         C_s[tid] = v;
         lval[((size_t)L * 2 + 1) * SE + tid] = v;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) __hip_atomic_store(&lflag[L], fP, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     // the next launch of the stream starts from here (a second slot: lines of this launch
@@ -692,6 +755,8 @@ struct erx_sdet {
     bool active = true;
     int drift_run = 0;
     long long checks = 0, drifts = 0, switched_at = -1;
+    double drift_sum = 0.0;
+    float drift_last = 0.f, drift_max = 0.f;
     erx_ctx* monitor = nullptr;  // plain ERX on the check lines
     erx_ctx* plain = nullptr;    // plain ERX after a switch (made up front: switching allocates nothing)
     hipStream_t stream = nullptr;
@@ -740,7 +805,7 @@ hipError_t net_forward(erx_surr* net, hipStream_t s, Erx16& erx, const float* X,
     const int ngrp = (p + 255) / 256;
     hipLaunchKernelGGL((k_surr_pix<false>), dim3((unsigned)((long long)n * ngrp)), dim3(256), 0, s, erx.Z, p, ngrp,
                        erx.Mt, erx.mu32, net->P, net->P16, net->off.A1, net->off.a1, net->off.w2, net->off.c2, out,
-                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f);
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.f, 0.f);
     return hipGetLastError();
 }
 
@@ -905,7 +970,7 @@ int erx_surrogate_train_step(erx_surr* net, const float* lines, const float* tar
     hipLaunchKernelGGL((k_surr_pix<true>), dim3((unsigned)nblk), dim3(256), 0, s, net->erx.Z, pixels, ngrp,
                        net->erx.Mt, net->erx.mu32, net->P, net->P16, net->off.A1, net->off.a1, net->off.w2,
                        net->off.c2, nullptr, targets, net->U, net->Pre, net->G, net->dZ, net->lossp,
-                       (float)(1.0 / (double)N));
+                       (float)(1.0 / (double)N), (float)(1.0 / (double)net->b));
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(256), 0, s, net->lossp, (int)nblk, 1LL, 1, net->loss);
     HIPCHK(hipGetLastError());
@@ -1052,6 +1117,9 @@ int erx_surrogate_detector_push(erx_sdet* sd, const float* lines, int n)
                 med = 0.5f * (med + lo);
             }
             ++sd->checks;
+            sd->drift_last = med;
+            sd->drift_sum += med;
+            sd->drift_max = std::isnan(med) || med > sd->drift_max ? med : sd->drift_max;
             const bool drift = !(med <= sd->theta);  // NaN counts as drift
             sd->drifts += drift ? 1 : 0;
             sd->drift_run = drift ? sd->drift_run + 1 : 0;
@@ -1076,6 +1144,16 @@ int erx_surrogate_detector_scores(erx_sdet* sd, float* out)
     HIPCHK(hipMemcpyAsync(out, sd->scores, (size_t)sd->last_n * sd->p * sizeof(float), hipMemcpyDefault,
                           sd->stream));
     HIPCHK(hipStreamSynchronize(sd->stream));
+    return ERX_OK;
+}
+
+int erx_surrogate_detector_drift_stats(const erx_sdet* sd, float* last, float* mean, float* max)
+{
+    if (!sd) return fail(ERX_EINVAL, "NULL detector");
+    if (sd->checks == 0) return fail(ERX_ESTATE, "no check line scored yet");
+    if (last) *last = sd->drift_last;
+    if (mean) *mean = (float)(sd->drift_sum / (double)sd->checks);
+    if (max) *max = sd->drift_max;
     return ERX_OK;
 }
 

@@ -94,3 +94,20 @@ def test_golden_worked_surrogate():
     P["w2"][:4] = [0.5, 0.25, 1.0, -0.2]
     got = S.forward(P, X, 0.1, ridge=0.0)["score"][0]
     np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
+
+
+def test_loss_weights_pixels_scored_above_the_background():
+    """Special cases of the weighted loss: targets below sqrt(b) weigh 1 (the plain mean
+    squared log error); a pixel whose target is 2 sqrt(b) counts four times; the weight
+    stops at 100 (targets of 10 sqrt(b) and beyond)."""
+    b = 16
+    X = data(1, 40, b, 5)
+    P = S.init_params(b, seed=3)
+    logs = np.log(S.forward(P, X, 0.2)["score"])
+    for scale, w in ((1.0, 1.0), (2.0, 4.0), (10.0, 100.0), (30.0, 100.0)):
+        target = np.full(logs.shape, 0.5 * np.sqrt(b))
+        target[0, 0] = scale * np.sqrt(b)
+        e2 = (logs - np.log(target)) ** 2
+        want = (e2.sum() + (w - 1.0) * e2[0, 0]) / e2.size
+        loss, _, _ = S.loss_and_grads(P, X, target, 0.2)
+        assert abs(loss - want) < 1e-12 * max(1.0, want), (scale, loss, want)
