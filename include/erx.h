@@ -118,6 +118,8 @@ typedef struct erx_config {
                           device memory and traffic of the statistics; the averaging recurrence of
                           Eqs. (20)-(21) is still evaluated in FP64 and each stored value is rounded
                           once).  erx_get_state / erx_set_state convert; not with ERX_BG_IMC */
+    int score_tiles;   /* tile shape of the split-FP16 score kernel: 16-pixel tiles per wave, 1 or 2;
+                          0 (default) = 2.  Results do not depend on it; erx_autotune chooses it */
 } erx_config;
 
 enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };
@@ -253,10 +255,11 @@ ERX_API void erx_batch_destroy(erx_batch *bt);
  * events on a stream of its own, and returns the fastest.  Candidates: for one stream,
  * lines per device pass (block_lines 512..8192) x scan segment (scan_lines 32, 64, 128);
  * for a batch, pass capacity (1024, 4096, 16384) and, when bands <= 16, the small-band
- * path mode (erx_batch_small_path 0, 1, 2).  No candidate changes what is computed: pass
- * and segment lengths only regroup the FP64 moving-average updates (scores agree with an
- * untuned handle's to 1e-6 relative), and the small-band modes agree with the general
- * path as erx_batch_small_path states.  The timings are those of well-conditioned
+ * path mode (erx_batch_small_path 0, 1, 2); with the split-FP16 score, each also x the
+ * score kernel's tile shape (score_tiles 1, 2).  No candidate changes what is computed:
+ * pass and segment lengths only regroup the FP64 moving-average updates (scores agree with
+ * an untuned handle's to 1e-6 relative), the tile shape changes no product, and the
+ * small-band modes agree with the general path as erx_batch_small_path states.  The timings are those of well-conditioned
  * backgrounds (no FP64 re-factor triggered).
  * ------------------------------------------------------------------------------------- */
 typedef struct erx_tune_result {
@@ -265,6 +268,7 @@ typedef struct erx_tune_result {
     int small_path;     /* erx_batch_small_path mode to use; -1 for a single stream */
     int candidates;     /* settings timed by this call; 0 when the result came from the cache */
     double us_per_line; /* measured microseconds per line (per stream line for a batch) */
+    int score_tiles;    /* erx_config.score_tiles to use */
 } erx_tune_result;
 /* cfg: the workload (its block_lines and scan_lines are ignored); nstreams >= 1 (1: a
  * detector made with erx_create_ex, more: a batch of that many streams of cfg's shape);

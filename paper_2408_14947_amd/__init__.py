@@ -55,7 +55,8 @@ class Config(C.Structure):
                 ("precision", C.c_int), ("fp64_cond_threshold", C.c_double),
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
                 ("cond_estimate", C.c_int), ("score_arith", C.c_int), ("srp_dims", C.c_int),
-                ("srp_seed", C.c_ulonglong), ("background", C.c_int), ("state_fp32", C.c_int)]
+                ("srp_seed", C.c_ulonglong), ("background", C.c_int), ("state_fp32", C.c_int),
+                ("score_tiles", C.c_int)]
 
 
 class DetectionMetrics(C.Structure):
@@ -66,7 +67,7 @@ class DetectionMetrics(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("block_lines", C.c_int), ("scan_lines", C.c_int), ("small_path", C.c_int),
-                ("candidates", C.c_int), ("us_per_line", C.c_double)]
+                ("candidates", C.c_int), ("us_per_line", C.c_double), ("score_tiles", C.c_int)]
 
 
 class KernelTime(C.Structure):
@@ -195,7 +196,7 @@ class Detector:
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
                  scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
                  score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0,
-                 background: str = "ema", state_fp32: bool = False):
+                 background: str = "ema", state_fp32: bool = False, score_tiles: int = 0):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
         stream, None = a stream owned by the handle.  srp_dims > 0: project every line
         to that many dimensions first (Sec. III-B, weights from srp_matrix).
@@ -217,6 +218,7 @@ class Detector:
         cfg.srp_seed = int(srp_seed)
         cfg.background = BACKGROUNDS[background]
         cfg.state_fp32 = 1 if state_fp32 else 0
+        cfg.score_tiles = int(score_tiles)
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
         self.work_bands = int(srp_dims) if srp_dims else int(bands)
@@ -341,7 +343,8 @@ class Batch:
                  precision: str = "split16",
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
                  scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True, score_arith: str = "split16",
-                 stream: Optional[int] = -1, small_path: int = -1, state_fp32: bool = False):
+                 stream: Optional[int] = -1, small_path: int = -1, state_fp32: bool = False,
+                 score_tiles: int = 0):
         lib = load()
         self.bands = [int(x) for x in bands]
         self.pixels = [int(x) for x in pixels]
@@ -360,6 +363,7 @@ class Batch:
         cfg.cond_estimate = int(cond_estimate)
         cfg.score_arith = SCORE_ARITH[score_arith]
         cfg.state_fp32 = 1 if state_fp32 else 0
+        cfg.score_tiles = int(score_tiles)
         b = (C.c_int * ns)(*self.bands)
         p = (C.c_int * ns)(*self.pixels)
         m = (C.c_float * ns)(*[float(x) for x in momentum])
@@ -569,14 +573,15 @@ def _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold,
 
 def _tune_dict(r):
     return {"block_lines": r.block_lines, "scan_lines": r.scan_lines, "small_path": r.small_path,
-            "candidates": r.candidates, "us_per_line": r.us_per_line}
+            "score_tiles": r.score_tiles, "candidates": r.candidates, "us_per_line": r.us_per_line}
 
 
 def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32", precision: str = "split16",
              fp64_cond_threshold: float = 0.0, normalise: bool = False, nstreams: int = 1,
              cache: Optional[str] = None) -> dict:
     """Fastest launch setting for a workload shape (erx_autotune): block_lines, scan_lines,
-    small_path (batch mode, -1 for one stream), candidates timed, us_per_line."""
+    small_path (batch mode, -1 for one stream), score_tiles (the score kernel's tile shape),
+    candidates timed, us_per_line."""
     lib = load()
     cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise)
     r = TuneResult()

@@ -40,6 +40,9 @@ struct BStream {
 
 struct Group {
     int NT = 0;
+    bool vecable = false;       // every stream of the group has a band count divisible by 4
+    hipStream_t gs = nullptr;   // the group's stream: groups run concurrently within a push
+    hipEvent_t done_ev = nullptr;
     long long E = 0;
     std::vector<int> streams;  // longest work first
     void* stats = nullptr;  // FP64, or FP32 with state_fp32
@@ -70,6 +73,7 @@ struct erx_batch {
     hipStream_t user = nullptr;        // the caller's stream (ordered with events)
     bool has_user = false;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t fork_ev = nullptr;      // the push's start, which every group stream waits for
     hipStream_t own_stream = nullptr;
     unsigned long long* ctr = nullptr;
     bool use_graphs = true;
@@ -91,6 +95,9 @@ void destroy_all(erx_batch* bt)
             if (g.slot_ev[k]) (void)hipEventDestroy(g.slot_ev[k]);
         }
         for (auto& kv : g.graphs) (void)hipGraphExecDestroy(kv.second);
+        if (g.gs) (void)hipStreamSynchronize(g.gs);
+        if (g.done_ev) (void)hipEventDestroy(g.done_ev);
+        if (g.gs) (void)hipStreamDestroy(g.gs);
     }
     for (auto& s : bt->st) {
         if (s.state) (void)hipFree(s.state);
@@ -100,6 +107,7 @@ void destroy_all(erx_batch* bt)
     if (bt->ctr) (void)hipFree(bt->ctr);
     if (bt->ev_in) (void)hipEventDestroy(bt->ev_in);
     if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
+    if (bt->fork_ev) (void)hipEventDestroy(bt->fork_ev);
     if (bt->own_stream) (void)hipStreamDestroy(bt->own_stream);
 }
 
@@ -136,7 +144,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
         c.precision < ERX_GRAM_FP32 || c.precision > ERX_GRAM_SPLIT16 || !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1) ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
-        c.background != ERX_BG_EMA || (c.state_fp32 != 0 && c.state_fp32 != 1)) {
+        c.background != ERX_BG_EMA || (c.state_fp32 != 0 && c.state_fp32 != 1) || c.score_tiles < 0 ||
+        c.score_tiles > 2) {
         fail(ERX_EINVAL, "erx_batch_create: invalid common configuration");
         return nullptr;
     }
@@ -154,18 +163,21 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     }
     bt->cfg = c;
     bt->st.resize(nstreams);
-    std::map<int, std::vector<int>> byNT;
+    // streams are grouped by tile count and by whether 4-band vector loads apply (a pass
+    // takes them only when all its streams allow them)
+    std::map<std::pair<int, int>, std::vector<int>> byNT;
     for (int s = 0; s < nstreams; ++s) {
         BStream& S = bt->st[s];
         S.b = bands[s];
         S.p = pixels[s];
         S.NT = (S.b + 15) / 16;
         S.alpha = momentum[s];
-        byNT[S.NT].push_back(s);
+        byNT[{S.NT, S.b % 4 == 0 ? 1 : 0}].push_back(s);
     }
     bool ok = hipStreamCreateWithFlags(&bt->own_stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&bt->ev_in, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&bt->fork_ev, hipEventDisableTiming) == hipSuccess;
     bt->stream = bt->own_stream;
     ok = ok && hipMalloc(&bt->ctr, 4 * sizeof(unsigned long long)) == hipSuccess &&
          hipMemset(bt->ctr, 0, 4 * sizeof(unsigned long long)) == hipSuccess;
@@ -174,7 +186,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
     for (auto& kv : byNT) {
         if (!ok) break;
         Group g;
-        g.NT = kv.first;
+        g.NT = kv.first.first;
+        g.vecable = kv.first.second != 0;
         g.E = stat_entries(g.NT);
         g.streams = kv.second;
         std::stable_sort(g.streams.begin(), g.streams.end(), [&](int a, int b2) {
@@ -191,6 +204,8 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
              hipMalloc(&g.mscale, C * sizeof(float)) == hipSuccess &&
              hipMalloc(&g.gredo, C * GRAM_MACROS_MAX * sizeof(int)) == hipSuccess &&
              hipMalloc(&g.flags, C * sizeof(int)) == hipSuccess && hipMalloc(&g.cond, C * sizeof(float)) == hipSuccess;
+        ok = ok && hipStreamCreateWithFlags(&g.gs, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&g.done_ev, hipEventDisableTiming) == hipSuccess;
         for (int k = 0; k < NSLOT && ok; ++k)
             ok = hipMalloc(&g.d_sd[k], ns * sizeof(StreamDesc)) == hipSuccess &&
                  hipHostMalloc(&g.h_sd[k], ns * sizeof(StreamDesc), hipHostMallocDefault) == hipSuccess &&
@@ -284,139 +299,167 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
     const bool fp64_pass = !std::isinf(thr);
     const int C = c.block_lines, seg = c.scan_lines;
 
-    for (Group& g : bt->groups) {
-        // (the fused kernels keep an FP64 state: with FP32 storage every group takes the general path)
-        if (g.NT == 1 && !c.state_fp32 &&
-            (bt->small_mode >= 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
-            // fused path: one launch, every stream's lines in order
-            const int slot = g.next_slot;
-            g.next_slot = (g.next_slot + 1) % NSLOT;
-            HIPCHK(hipEventSynchronize(g.slot_ev[slot]));
-            StreamDesc* hd = g.h_sd[slot];
-            int nsd = 0, vec4 = 1, pmax = 0, lmax = 0, al16 = bt->small_mode != 2;
-            for (int s : g.streams) {
-                if (nlines[s] == 0) continue;
-                BStream& B = bt->st[s];
-                StreamDesc d{};
-                d.x = lines[s];
-                d.out = B.scores;
-                d.outn = c.normalise ? B.scores_n : nullptr;
-                d.state = B.state;
-                d.t0 = B.t;
-                d.alpha = B.alpha;
-                d.eps = c.ridge;
-                d.p = B.p;
-                d.b = B.b;
-                d.n = nlines[s];
-                hd[nsd++] = d;
-                vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)lines[s] % (4 * esz)) == 0;
-                pmax = std::max(pmax, B.p);
-                const long long lb = (long long)B.p * B.b * esz;  // bytes of one line
-                al16 = al16 && lb % 16 == 0 && (uintptr_t)lines[s] % 16 == 0;
-                lmax = (int)std::min<long long>(std::max<long long>(lmax, lb), 1LL << 30);
-                B.t += nlines[s];
+    // every group runs on its own stream from the push's start (fork) and the push ends when
+    // all of them have (join): groups of different tile counts overlap on the device
+    // The host deals one pass to each group in turn, so that every group has work queued
+    // while it waits for a descriptor slot of another.
+    HIPCHK(hipEventRecord(bt->fork_ev, bt->stream));
+    const size_t ng = bt->groups.size();
+    std::vector<std::vector<int>> offs(ng);
+    std::vector<char> live(ng, 1);
+    for (size_t gi = 0; gi < ng; ++gi) {
+        HIPCHK(hipStreamWaitEvent(bt->groups[gi].gs, bt->fork_ev, 0));
+        offs[gi].assign(bt->groups[gi].streams.size(), 0);
+    }
+    for (bool any = true; any;) {
+        any = false;
+        for (size_t gi = 0; gi < ng; ++gi) {
+            if (!live[gi]) continue;
+            Group& g = bt->groups[gi];
+            hipStream_t gstream = g.gs;
+            // (the fused kernels keep an FP64 state: with FP32 storage every group takes the general path)
+            if (g.NT == 1 && !c.state_fp32 &&
+                (bt->small_mode >= 1 || (bt->small_mode == -1 && g.streams.size() >= 32))) {
+                // fused path: one launch, every stream's lines in order
+                const int slot = g.next_slot;
+                g.next_slot = (g.next_slot + 1) % NSLOT;
+                HIPCHK(hipEventSynchronize(g.slot_ev[slot]));
+                StreamDesc* hd = g.h_sd[slot];
+                int nsd = 0, vec4 = 1, pmax = 0, lmax = 0, al16 = bt->small_mode != 2;
+                for (int s : g.streams) {
+                    if (nlines[s] == 0) continue;
+                    BStream& B = bt->st[s];
+                    StreamDesc d{};
+                    d.x = lines[s];
+                    d.out = B.scores;
+                    d.outn = c.normalise ? B.scores_n : nullptr;
+                    d.state = B.state;
+                    d.t0 = B.t;
+                    d.alpha = B.alpha;
+                    d.eps = c.ridge;
+                    d.p = B.p;
+                    d.b = B.b;
+                    d.n = nlines[s];
+                    hd[nsd++] = d;
+                    vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)lines[s] % (4 * esz)) == 0;
+                    pmax = std::max(pmax, B.p);
+                    const long long lb = (long long)B.p * B.b * esz;  // bytes of one line
+                    al16 = al16 && lb % 16 == 0 && (uintptr_t)lines[s] % 16 == 0;
+                    lmax = (int)std::min<long long>(std::max<long long>(lmax, lb), 1LL << 30);
+                    B.t += nlines[s];
+                }
+                if (nsd > 0) {
+                    Pass P{};
+                    P.sd = g.d_sd[slot];
+                    P.nstreams = nsd;
+                    P.pmax = pmax;
+                    P.vec4 = vec4;
+                    HIPCHK(hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
+                                          gstream));
+                    HIPCHK(launch_small(c.dtype, P, c.normalise, bt->ctr, al16 ? lmax : 0, gstream));
+                }
+                HIPCHK(hipEventRecord(g.slot_ev[slot], gstream));
+                HIPCHK(hipEventRecord(g.done_ev, gstream));
+                HIPCHK(hipStreamWaitEvent(bt->stream, g.done_ev, 0));
+                live[gi] = 0;
+                continue;
             }
-            if (nsd > 0) {
+            std::vector<int>& off = offs[gi];
+            {
+                // streams with lines left, longest work first
+                std::vector<int> act;
+                for (size_t k = 0; k < g.streams.size(); ++k)
+                    if (off[k] < nlines[g.streams[k]]) act.push_back((int)k);
+                if (act.empty()) {  // the group is done: the push's end waits for it
+                    HIPCHK(hipEventRecord(g.done_ev, gstream));
+                    HIPCHK(hipStreamWaitEvent(bt->stream, g.done_ev, 0));
+                    live[gi] = 0;
+                    continue;
+                }
+                any = true;
+                int quota = C / (int)act.size();
+                quota = quota >= seg ? (quota / seg) * seg : seg;
+                // descriptors
+                const int slot = g.next_slot;
+                g.next_slot = (g.next_slot + 1) % NSLOT;
+                HIPCHK(hipEventSynchronize(g.slot_ev[slot]));  // the slot's previous upload has run
+                StreamDesc* hd = g.h_sd[slot];
+                int L = 0, S = 0, nsd = 0, pmax = 0, vec4 = 1;
+                std::vector<std::pair<int, int>> taken;  // (group index, lines)
+                for (int k : act) {
+                    const int s = g.streams[k];
+                    const BStream& B = bt->st[s];
+                    int kl = std::min(nlines[s] - off[k], quota);
+                    if (L + kl > C) kl = C - L;
+                    if (kl <= 0) break;
+                    StreamDesc d{};
+                    d.x = (const char*)lines[s] + (size_t)off[k] * B.p * B.b * esz;
+                    d.out = B.scores + (size_t)off[k] * B.p;
+                    d.outn = c.normalise ? B.scores_n + (size_t)off[k] * B.p : nullptr;
+                    d.state = B.state;
+                    d.t0 = B.t;
+                    d.alpha = B.alpha;
+                    d.eps = c.ridge;
+                    d.p = B.p;
+                    d.b = B.b;
+                    d.n = kl;
+                    d.line0 = L;
+                    d.seg0 = S;
+                    hd[nsd++] = d;
+                    L += kl;
+                    S += (kl + seg - 1) / seg;
+                    pmax = std::max(pmax, B.p);
+                    vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)d.x % (4 * esz)) == 0;
+                    taken.push_back({k, kl});
+                }
                 Pass P{};
                 P.sd = g.d_sd[slot];
                 P.nstreams = nsd;
+                P.nlines = L;
+                P.nseg = S;
+                P.seg = seg;
                 P.pmax = pmax;
                 P.vec4 = vec4;
-                HIPCHK(hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
-                                      bt->stream));
-                HIPCHK(launch_small(c.dtype, P, c.normalise, bt->ctr, al16 ? lmax : 0, bt->stream));
-            }
-            HIPCHK(hipEventRecord(g.slot_ev[slot], bt->stream));
-            continue;
-        }
-        std::vector<int> off(g.streams.size(), 0);
-        for (;;) {
-            // streams with lines left, longest work first
-            std::vector<int> act;
-            for (size_t k = 0; k < g.streams.size(); ++k)
-                if (off[k] < nlines[g.streams[k]]) act.push_back((int)k);
-            if (act.empty()) break;
-            int quota = C / (int)act.size();
-            quota = quota >= seg ? (quota / seg) * seg : seg;
-            // descriptors
-            const int slot = g.next_slot;
-            g.next_slot = (g.next_slot + 1) % NSLOT;
-            HIPCHK(hipEventSynchronize(g.slot_ev[slot]));  // the slot's previous upload has run
-            StreamDesc* hd = g.h_sd[slot];
-            int L = 0, S = 0, nsd = 0, pmax = 0, vec4 = 1;
-            std::vector<std::pair<int, int>> taken;  // (group index, lines)
-            for (int k : act) {
-                const int s = g.streams[k];
-                const BStream& B = bt->st[s];
-                int kl = std::min(nlines[s] - off[k], quota);
-                if (L + kl > C) kl = C - L;
-                if (kl <= 0) break;
-                StreamDesc d{};
-                d.x = (const char*)lines[s] + (size_t)off[k] * B.p * B.b * esz;
-                d.out = B.scores + (size_t)off[k] * B.p;
-                d.outn = c.normalise ? B.scores_n + (size_t)off[k] * B.p : nullptr;
-                d.state = B.state;
-                d.t0 = B.t;
-                d.alpha = B.alpha;
-                d.eps = c.ridge;
-                d.p = B.p;
-                d.b = B.b;
-                d.n = kl;
-                d.line0 = L;
-                d.seg0 = S;
-                hd[nsd++] = d;
-                L += kl;
-                S += (kl + seg - 1) / seg;
-                pmax = std::max(pmax, B.p);
-                vec4 = vec4 && (B.b % 4 == 0) && ((uintptr_t)d.x % (4 * esz)) == 0;
-                taken.push_back({k, kl});
-            }
-            Pass P{};
-            P.sd = g.d_sd[slot];
-            P.nstreams = nsd;
-            P.nlines = L;
-            P.nseg = S;
-            P.seg = seg;
-            P.pmax = pmax;
-            P.vec4 = vec4;
-            P.mscale = g.mscale;
-            P.gredo = g.gredo;
-            P.sf32 = c.state_fp32;
-            auto record = [&]() -> hipError_t {
-                hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
-                                              bt->stream);
-                if (e != hipSuccess) return e;
-                return run_pass(bt->stream, P, g.NT, c.dtype, c.precision, c.score_arith, g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, thr,
-                                want_cond, fp64_pass, c.normalise != 0, bt->ctr, nullptr);
-            };
-            if (bt->use_graphs) {
-                const auto key = std::make_tuple(slot, nsd, L, S, pmax, vec4);
-                auto it = g.graphs.find(key);
-                if (it == g.graphs.end()) {
-                    hipGraph_t graph;
-                    HIPCHK(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
-                    const hipError_t e = record();
-                    hipGraph_t got = nullptr;
-                    const hipError_t e2 = hipStreamEndCapture(bt->stream, &got);  // always ends the capture
-                    if (e != hipSuccess || e2 != hipSuccess) {
-                        if (got) (void)hipGraphDestroy(got);
-                        return fail(ERX_EDEVICE, "graph capture failed: %s", hipGetErrorString(e ? e : e2));
+                P.mscale = g.mscale;
+                P.gredo = g.gredo;
+                P.sf32 = c.state_fp32;
+                P.spt = c.score_tiles;
+                auto record = [&]() -> hipError_t {
+                    hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
+                                                  gstream);
+                    if (e != hipSuccess) return e;
+                    return run_pass(gstream, P, g.NT, c.dtype, c.precision, c.score_arith, g.stats, g.carry, g.Mt, g.mu32, g.flags, g.cond, thr,
+                                    want_cond, fp64_pass, c.normalise != 0, bt->ctr, nullptr);
+                };
+                if (bt->use_graphs) {
+                    const auto key = std::make_tuple(slot, nsd, L, S, pmax, vec4);
+                    auto it = g.graphs.find(key);
+                    if (it == g.graphs.end()) {
+                        hipGraph_t graph;
+                        HIPCHK(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal));
+                        const hipError_t e = record();
+                        hipGraph_t got = nullptr;
+                        const hipError_t e2 = hipStreamEndCapture(gstream, &got);  // always ends the capture
+                        if (e != hipSuccess || e2 != hipSuccess) {
+                            if (got) (void)hipGraphDestroy(got);
+                            return fail(ERX_EDEVICE, "graph capture failed: %s", hipGetErrorString(e ? e : e2));
+                        }
+                        graph = got;
+                        hipGraphExec_t exec;
+                        const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(graph);
+                        if (e3 != hipSuccess) return fail(ERX_EDEVICE, "graph instantiation failed");
+                        it = g.graphs.emplace(key, exec).first;
                     }
-                    graph = got;
-                    hipGraphExec_t exec;
-                    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                    (void)hipGraphDestroy(graph);
-                    if (e3 != hipSuccess) return fail(ERX_EDEVICE, "graph instantiation failed");
-                    it = g.graphs.emplace(key, exec).first;
+                    HIPCHK(hipGraphLaunch(it->second, gstream));
+                } else {
+                    HIPCHK(record());
                 }
-                HIPCHK(hipGraphLaunch(it->second, bt->stream));
-            } else {
-                HIPCHK(record());
-            }
-            HIPCHK(hipEventRecord(g.slot_ev[slot], bt->stream));
-            for (auto& tk : taken) {
-                off[tk.first] += tk.second;
-                bt->st[g.streams[tk.first]].t += tk.second;
+                HIPCHK(hipEventRecord(g.slot_ev[slot], gstream));
+                for (auto& tk : taken) {
+                    off[tk.first] += tk.second;
+                    bt->st[g.streams[tk.first]].t += tk.second;
+                }
             }
         }
     }

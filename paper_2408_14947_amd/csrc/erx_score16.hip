@@ -69,13 +69,16 @@ __device__ __forceinline__ HL split16(const f4 v, float s)
 
 }  // namespace
 
-template <int NT, int DT, bool VEC>
-__global__ __launch_bounds__(256, NT <= 14 ? 3 : 2) void k_score16(const Pass P, const float* __restrict__ Mt,
+// PT: 16-pixel tiles per wave (the tile shape the autotuner chooses: one tile keeps
+// fewer accumulators per lane and more workgroups per line, two reuse each staged M tile
+// for twice the pixels)
+template <int NT, int DT, bool VEC, int PT>
+__global__ __launch_bounds__(256, PT == 1 ? (NT <= 13 ? 4 : 3) : (NT <= 14 ? 3 : 2)) void k_score16(const Pass P,
+                                                                                   const float* __restrict__ Mt,
                                                                     const float* __restrict__ mu32,
                                                                     int* __restrict__ flags, int ngrp)
 {
     constexpr int NTL = NT * (NT + 1) / 2;
-    constexpr int PT = SCORE_PT;
     constexpr int MR = (NT * 64 + 255) / 256;  // rounds of 256 threads to stage the longest column
     // all pixel groups of a line on one XCD (block ids are dealt to the 8 XCDs
     // round robin), so the line's M tiles are fetched into one L2
@@ -204,14 +207,21 @@ __global__ __launch_bounds__(256, NT <= 14 ? 3 : 2) void k_score16(const Pass P,
     }
 }
 
+template <int NT, int DT, int PT>
+static void score16_pt(const Pass& P, const float* Mt, const float* mu32, int* flags, hipStream_t s)
+{
+    const int per = 4 * PT * 16;
+    const int ngrp = (P.pmax + per - 1) / per;
+    const dim3 grid((unsigned)((long long)(P.nlines + 7) / 8 * 8 * ngrp));
+    if (P.vec4) hipLaunchKernelGGL((k_score16<NT, DT, true, PT>), grid, dim3(256), 0, s, P, Mt, mu32, flags, ngrp);
+    else hipLaunchKernelGGL((k_score16<NT, DT, false, PT>), grid, dim3(256), 0, s, P, Mt, mu32, flags, ngrp);
+}
+
 template <int NT, int DT>
 static void score16_one(const Pass& P, const float* Mt, const float* mu32, int* flags, hipStream_t s)
 {
-    const int per = 4 * SCORE_PT * 16;
-    const int ngrp = (P.pmax + per - 1) / per;
-    const dim3 grid((unsigned)((long long)(P.nlines + 7) / 8 * 8 * ngrp));
-    if (P.vec4) hipLaunchKernelGGL((k_score16<NT, DT, true>), grid, dim3(256), 0, s, P, Mt, mu32, flags, ngrp);
-    else hipLaunchKernelGGL((k_score16<NT, DT, false>), grid, dim3(256), 0, s, P, Mt, mu32, flags, ngrp);
+    if (P.spt == 1) score16_pt<NT, DT, 1>(P, Mt, mu32, flags, s);
+    else score16_pt<NT, DT, SCORE_PT>(P, Mt, mu32, flags, s);
 }
 
 template <int DT, int... NTs>

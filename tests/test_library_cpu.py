@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol():
                                          ("momentum", float("nan")), ("ridge", -1e-3),
                                          ("dtype", 7), ("precision", 4), ("block_lines", 0), ("scan_lines", 0),
                                          ("warmup", -1), ("fp64_cond_threshold", -1.0),
-                                         ("cond_estimate", 2), ("state_fp32", 2)])
+                                         ("cond_estimate", 2), ("state_fp32", 2), ("score_tiles", 3)])
 def test_create_rejects_invalid_config(field, value):
     erx, lib = _lib()
     cfg = erx.Config()
@@ -117,7 +117,8 @@ def test_tune_cache_lookup(tmp_path):
                 '"fp64_cond_threshold": 0, "block_lines": 1024, "scan_lines": 64, "small_path": 1, '
                 '"us_per_line": 0.04}\n]}\n')
     r = erx.tune_lookup(224, 1024, path)
-    assert r == {"block_lines": 4096, "scan_lines": 32, "small_path": -1, "candidates": 0, "us_per_line": 11.5}
+    assert r == {"block_lines": 4096, "scan_lines": 32, "small_path": -1, "score_tiles": 0, "candidates": 0,
+                 "us_per_line": 11.5}
     r = erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1024)
     assert r["small_path"] == 1 and r["block_lines"] == 1024
     assert erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1) is None        # other stream count
