@@ -46,7 +46,12 @@ def short_kernel(name):
     k = m.group(1)
     if k == "chol":
         return "chol_fp64" if (m.group(3) or "").startswith("double") else "chol_fp32"
-    return {"gram4": "gram"}.get(k, k)
+    if k == "gram4":  # template arguments <dtype, precision, vec>: precision 0 is the FP32 Gram
+        args = (m.group(3) or "").replace(" ", "").split(",")
+        return "gram_fp32" if len(args) > 1 and args[1] == "0" else "gram"
+    # the library's profiler names: the split-FP16 score kernel is "score", the FP32 one runs
+    # after it for the lines it flags
+    return {"gram4": "gram", "score16": "score", "score": "score_fp32_redo"}.get(k, k)
 
 
 def _csv_rows(d, suffix):
@@ -141,24 +146,54 @@ def load_traffic(kernel, block_lines):
         return None
     if rec.get("source_sha256") != kernel_source_hash() or rec.get("block_lines") != block_lines:
         return None
+    if kernel == "gram":  # the library's Gram launch is the split-FP16 pass plus the FP32 pass it leaves
+        es = [rec["kernels"][k] for k in ("gram", "gram_fp32") if k in rec["kernels"]]
+        return sum(e["bytes"] for e in es) if es else None
     e = rec["kernels"].get(kernel)
     return None if e is None else e["bytes"]
 
 
-def kernel_work(name, b, p):
-    """(bound, algorithmic amount per line, unit) of one kernel."""
-    if name == "gram":       # symmetric half of X^T X: p * b(b+1)/2 multiply-adds
-        return "mfma", p * b * (b + 1), "flop"
-    if name == "score":      # lower-triangular L^-1 r per pixel, residual, squares and sum
-        return "mfma", p * b * (b + 1) + 3 * p * b, "flop"
-    if name in ("chol_fp32", "chol_fp64"):  # Cholesky + triangular inverse
-        return "mfma", 2 * b ** 3 / 3, "flop"
-    if name in ("scan_local",):             # read + write the FP64 packed statistics
-        e = ((b + 15) // 16) * ((b + 15) // 16 + 1) // 2 * 256 + 16 * ((b + 15) // 16)
-        return "hbm", 2 * 8 * e, "byte"
+# dense peaks of the units each kernel computes on (TFLOP/s): FP32 MFMA, FP64 MFMA, FP16 MFMA;
+# a split-FP16 product takes three FP16 products, so its algorithmic flops meet a third of it
+MFMA_PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "split16": 2500.0 / 3.0}
+
+
+def kernel_work(name, b, p, gram="split16", score="split16", state_bytes=8):
+    """Algorithmic work of one kernel per line: {"flop": F, "byte": B, "peak_tflops": P} with P the
+    dense peak of the unit it computes on (None for a kernel with no arithmetic to speak of)."""
+    nt = (b + 15) // 16
+    ntl = nt * (nt + 1) // 2
+    e = ntl * 256 + 16 * nt                     # packed statistics per line
+    line = p * b * 4                            # one FP32 line
+    if name == "gram":       # symmetric half of X^T X: p * b(b+1)/2 multiply-adds; line in, statistics out
+        return {"flop": p * b * (b + 1), "byte": line + e * state_bytes, "peak_tflops": MFMA_PEAK[gram]}
+    if name == "score":      # L^-1 r per pixel, residual, squares and sum
+        return {"flop": p * b * (b + 1) + 3 * p * b, "byte": line + 4 * p + ntl * 256 * 4 + 16 * nt * 4,
+                "peak_tflops": MFMA_PEAK["split16" if score == "split16" else "fp32"]}
+    if name == "score_fp32_redo":  # only the lines the split kernel flagged: no per-line figure
+        return {"flop": 0, "byte": 0, "peak_tflops": None}
+    if name in ("chol_fp32", "chol_fp64"):      # Cholesky + triangular inverse; statistics in, factor out
+        return {"flop": 2 * b ** 3 / 3, "byte": 2 * e * state_bytes + ntl * 256 * 4,
+                "peak_tflops": MFMA_PEAK["fp64" if name == "chol_fp64" else "fp32"]}
+    if name == "scan_local":                    # read + write the packed statistics
+        return {"flop": 0, "byte": 2 * state_bytes * e, "peak_tflops": None}
     if name == "scan_carry":
-        return "hbm", 0, "byte"
-    return "hbm", 4 * p, "byte"
+        return {"flop": 0, "byte": 0, "peak_tflops": None}
+    return {"flop": 0, "byte": 4 * p, "peak_tflops": None}
+
+
+def roof(work, lines, seconds):
+    """The binding roof of a kernel that did `work` per line for `lines` lines in `seconds`:
+    the larger of its compute floor and its HBM floor, with what it achieved against it."""
+    t_mem = work["byte"] * lines / (PEAK["hbm_gbs"] * 1e9)
+    t_cmp = work["flop"] * lines / (work["peak_tflops"] * 1e12) if work["peak_tflops"] else 0.0
+    if t_cmp > t_mem:
+        ach = work["flop"] * lines / seconds / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": work["peak_tflops"], "unit": "TFLOP/s",
+                "frac": ach / work["peak_tflops"], "floor_ms": t_cmp * 1e3}
+    ach = work["byte"] * lines / seconds / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+            "frac": ach / PEAK["hbm_gbs"], "floor_ms": t_mem * 1e3}
 
 
 def time_workload(erx, torch, X, b, p, momentum, steps, warmup, block_lines, stream, profile, **kw):
@@ -608,7 +643,7 @@ def mixed_leg(erx, torch, X, b, p, momentum, args, stream, plain_ms, plain_prof,
             emax, emed = float(e.max()), float(e.median())
         torch.cuda.synchronize()
         gram_ms = prof["gram"][1] / prof["gram"][0]
-        flops = kernel_work("gram", b, p)[1] * T * args.steps / prof["gram"][0]
+        flops = kernel_work("gram", b, p)["flop"] * T * args.steps / prof["gram"][0]
         res[prec] = {"ms_per_step": ms / args.steps, "pixels_per_s": T * p * args.steps / (ms / 1e3),
                      "speedup_vs_plain": plain_ms / (ms / args.steps),
                      "gram_ms": gram_ms, "gram_tflops": flops / (gram_ms / 1e3) / 1e12,
@@ -709,29 +744,23 @@ def main():
     for name, (n, tot) in prof.items():
         kernels[name] = {"launches": n, "avg_ms": tot / n, "total_ms": tot}
     dom = max(prof, key=lambda k: prof[k][1])
-    bound, per_line, unit = kernel_work(dom, b, p)
+    for name, kv in kernels.items():
+        lpl = T * args.steps / kv["launches"]
+        kv.update({k: v for k, v in roof(kernel_work(name, b, p), lpl, kv["avg_ms"] / 1e3).items()})
     n_l, tot_ms = prof[dom]
     lines_per_launch = T * args.steps / n_l
-    work_launch = per_line * lines_per_launch
-    avg_s = tot_ms / n_l / 1e3
-    if unit == "flop":
-        achieved = work_launch / avg_s / 1e12
-        peak = PEAK["fp32_mfma_tflops"]
-        runit = "TFLOP/s"
-    else:
-        achieved = work_launch / avg_s / 1e9
-        peak = PEAK["hbm_gbs"]
-        runit = "GB/s"
-    for name, kv in kernels.items():
-        bd, pl, un = kernel_work(name, b, p)
-        lpl = T * args.steps / kv["launches"]
-        rate = pl * lpl / (kv["avg_ms"] / 1e3)
-        kv["achieved"] = rate / (1e12 if un == "flop" else 1e9)
-        kv["unit"] = "TFLOP/s" if un == "flop" else "GB/s"
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": runit,
-                "frac": round(achieved / peak, 4), "traffic": load_traffic(dom, args.block_lines),
+    w = kernel_work(dom, b, p)
+    r = roof(w, lines_per_launch, tot_ms / n_l / 1e3)
+    roofline = {"bound": r["bound"], "achieved": round(r["achieved"], 3), "peak": r["peak"], "unit": r["unit"],
+                "frac": round(r["frac"], 4), "traffic": load_traffic(dom, args.block_lines),
                 "traffic_unit": "bytes/launch", "kernel": dom,
-                "work_per_launch": work_launch, "lines_per_launch": lines_per_launch}
+                "work_per_launch": (w["byte"] if r["bound"] == "hbm" else w["flop"]) * lines_per_launch,
+                "work_unit": "byte" if r["bound"] == "hbm" else "flop", "lines_per_launch": lines_per_launch,
+                "floor_ms": r["floor_ms"]}
+    if dom == "gram":
+        roofline["note"] = ("split-FP16 Gram: three FP16 products per product, so its compute floor is the "
+                            "algorithmic flops at a third of the FP16 peak; its HBM floor (line in, FP64 "
+                            "statistics out) is the larger")
 
     out = {
         "metric": METRIC, "value": pix_s, "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,

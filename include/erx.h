@@ -119,7 +119,8 @@ typedef struct erx_config {
                           Eqs. (20)-(21) is still evaluated in FP64 and each stored value is rounded
                           once).  erx_get_state / erx_set_state convert; not with ERX_BG_IMC */
     int score_tiles;   /* tile shape of the split-FP16 score kernel: 16-pixel tiles per wave, 1 or 2;
-                          0 (default) = 2.  Results do not depend on it; erx_autotune chooses it */
+                          0 (default): 1 above 192 bands (where two would spill registers), else 2.
+                          Results do not depend on it; erx_autotune chooses it */
 } erx_config;
 
 enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };

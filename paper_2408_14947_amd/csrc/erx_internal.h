@@ -57,8 +57,8 @@ struct Pass {
                            // split-FP16 Gram left it to the FP32 pass; null: no split Gram
     int sf32;              // 1: statistics, carries and states are stored in FP32 (the
                            // averaging itself still runs in FP64); 0: FP64 storage
-    int spt;               // 16-pixel tiles per wave of the split-FP16 score kernel: 1, or
-                           // anything else for SCORE_PT
+    int spt;               // 16-pixel tiles per wave of the split-FP16 score kernel: 1, 2, or 0
+                           // for 1 from 13 band tiles on and SCORE_PT below
 };
 constexpr int GRAM_MACROS_MAX = 15;  // upper 64x64 macro tiles of a 304-band Gram
 

@@ -220,7 +220,8 @@ static void score16_pt(const Pass& P, const float* Mt, const float* mu32, int* f
 template <int NT, int DT>
 static void score16_one(const Pass& P, const float* Mt, const float* mu32, int* flags, hipStream_t s)
 {
-    if (P.spt == 1) score16_pt<NT, DT, 1>(P, Mt, mu32, flags, s);
+    // default: one tile per wave from 13 band tiles on, where two would spill registers
+    if (P.spt == 1 || (P.spt == 0 && NT >= 13)) score16_pt<NT, DT, 1>(P, Mt, mu32, flags, s);
     else score16_pt<NT, DT, SCORE_PT>(P, Mt, mu32, flags, s);
 }
 
