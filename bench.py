@@ -757,6 +757,15 @@ def main():
                 "work_per_launch": (w["byte"] if r["bound"] == "hbm" else w["flop"]) * lines_per_launch,
                 "work_unit": "byte" if r["bound"] == "hbm" else "flop", "lines_per_launch": lines_per_launch,
                 "floor_ms": r["floor_ms"]}
+    # the scoring kernel against its own roof (the brief's scoring target is a fraction of HBM)
+    if "score" in prof:
+        n_s, tot_s = prof["score"]
+        rs = roof(kernel_work("score", b, p), T * args.steps / n_s, tot_s / n_s / 1e3)
+        scoring = {"kernel": "score", "bound": rs["bound"], "achieved": round(rs["achieved"], 3),
+                   "peak": rs["peak"], "unit": rs["unit"], "frac": round(rs["frac"], 4),
+                   "traffic": load_traffic("score", args.block_lines), "traffic_unit": "bytes/launch"}
+    else:
+        scoring = None
     if dom == "gram":
         roofline["note"] = ("split-FP16 Gram: three FP16 products per product, so its compute floor is the "
                             "algorithmic flops at a third of the FP16 peak; its HBM floor (line in, FP64 "
@@ -769,7 +778,8 @@ def main():
         "config": {"workload": WORKLOAD,
                    "lines": T, "pixels": p, "bands": b, "block_lines": args.block_lines,
                    "fp64_cond_threshold": 0.0 if args.fp64_threshold is None else args.fp64_threshold},
-        "lines_per_s": lines_s, "wall_s": wall, "roofline": roofline, "kernels": kernels,
+        "lines_per_s": lines_s, "wall_s": wall, "roofline": roofline, "scoring_roofline": scoring,
+        "kernels": kernels,
         "fp64_refactors": st["fp64_refactors"], "max_cond": st["max_cond"],
     }
     # the headline path's own scores against the FP64 oracle on the checked windows
