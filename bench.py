@@ -666,6 +666,10 @@ def main():
     ap.add_argument("--block-lines", type=int, default=4096)
     ap.add_argument("--fp64-threshold", type=float, default=None,
                     help="condition-estimate threshold for the FP64 re-factor (library default if unset)")
+    ap.add_argument("--precision", default=None, choices=("fp32", "bf16", "fp16", "split16"),
+                    help="Gram arithmetic of the headline path (library default, split16, if unset)")
+    ap.add_argument("--state-fp32", action="store_true",
+                    help="headline path with FP32 statistics, carries and state")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -733,6 +737,10 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} steps after {args.warmup} warm-up steps", file=sys.stderr, flush=True)
     kw = {} if args.fp64_threshold is None else {"fp64_cond_threshold": args.fp64_threshold}
+    if args.precision:
+        kw["precision"] = args.precision
+    if args.state_fp32:
+        kw["state_fp32"] = True
     ms, wall, prof, st = time_workload(erx, torch, X, b, p, sc.momentum, args.steps, args.warmup,
                                        args.block_lines, stream, profile=True, **kw)
     ms_step = ms / args.steps
@@ -744,15 +752,18 @@ def main():
     for name, (n, tot) in prof.items():
         kernels[name] = {"launches": n, "avg_ms": tot / n, "total_ms": tot}
     dom = max(prof, key=lambda k: prof[k][1])
+    # the run's arithmetic (the counter record belongs to the default configuration only)
+    wk = {"gram": args.precision or "split16", "state_bytes": 4 if args.state_fp32 else 8}
+    default_cfg = not args.precision and not args.state_fp32
     for name, kv in kernels.items():
         lpl = T * args.steps / kv["launches"]
-        kv.update({k: v for k, v in roof(kernel_work(name, b, p), lpl, kv["avg_ms"] / 1e3).items()})
+        kv.update({k: v for k, v in roof(kernel_work(name, b, p, **wk), lpl, kv["avg_ms"] / 1e3).items()})
     n_l, tot_ms = prof[dom]
     lines_per_launch = T * args.steps / n_l
-    w = kernel_work(dom, b, p)
+    w = kernel_work(dom, b, p, **wk)
     r = roof(w, lines_per_launch, tot_ms / n_l / 1e3)
     roofline = {"bound": r["bound"], "achieved": round(r["achieved"], 3), "peak": r["peak"], "unit": r["unit"],
-                "frac": round(r["frac"], 4), "traffic": load_traffic(dom, args.block_lines),
+                "frac": round(r["frac"], 4), "traffic": load_traffic(dom, args.block_lines) if default_cfg else None,
                 "traffic_unit": "bytes/launch", "kernel": dom,
                 "work_per_launch": (w["byte"] if r["bound"] == "hbm" else w["flop"]) * lines_per_launch,
                 "work_unit": "byte" if r["bound"] == "hbm" else "flop", "lines_per_launch": lines_per_launch,
@@ -760,13 +771,14 @@ def main():
     # the scoring kernel against its own roof (the brief's scoring target is a fraction of HBM)
     if "score" in prof:
         n_s, tot_s = prof["score"]
-        rs = roof(kernel_work("score", b, p), T * args.steps / n_s, tot_s / n_s / 1e3)
+        rs = roof(kernel_work("score", b, p, **wk), T * args.steps / n_s, tot_s / n_s / 1e3)
         scoring = {"kernel": "score", "bound": rs["bound"], "achieved": round(rs["achieved"], 3),
                    "peak": rs["peak"], "unit": rs["unit"], "frac": round(rs["frac"], 4),
-                   "traffic": load_traffic("score", args.block_lines), "traffic_unit": "bytes/launch"}
+                   "traffic": load_traffic("score", args.block_lines) if default_cfg else None,
+                   "traffic_unit": "bytes/launch"}
     else:
         scoring = None
-    if dom == "gram":
+    if dom == "gram" and wk["gram"] == "split16":
         roofline["note"] = ("split-FP16 Gram: three FP16 products per product, so its compute floor is the "
                             "algorithmic flops at a third of the FP16 peak; its HBM floor (line in, FP64 "
                             "statistics out) is the larger")
@@ -777,7 +789,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD,
                    "lines": T, "pixels": p, "bands": b, "block_lines": args.block_lines,
-                   "fp64_cond_threshold": 0.0 if args.fp64_threshold is None else args.fp64_threshold},
+                   "fp64_cond_threshold": 0.0 if args.fp64_threshold is None else args.fp64_threshold,
+                   "gram": args.precision or "split16", "state": "fp32" if args.state_fp32 else "fp64"},
         "lines_per_s": lines_s, "wall_s": wall, "roofline": roofline, "scoring_roofline": scoring,
         "kernels": kernels,
         "fp64_refactors": st["fp64_refactors"], "max_cond": st["max_cond"],
