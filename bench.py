@@ -663,7 +663,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--block-lines", type=int, default=4096)
+    ap.add_argument("--block-lines", type=int, default=1024,
+                    help="lines per device pass of the headline path (the autotuner's choice for this shape)")
     ap.add_argument("--fp64-threshold", type=float, default=None,
                     help="condition-estimate threshold for the FP64 re-factor (library default if unset)")
     ap.add_argument("--precision", default=None, choices=("fp32", "bf16", "fp16", "split16"),
