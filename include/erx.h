@@ -274,8 +274,8 @@ typedef struct erx_tune_result {
 /* cfg: the workload (its block_lines and scan_lines are ignored); nstreams >= 1 (1: a
  * detector made with erx_create_ex, more: a batch of that many streams of cfg's shape);
  * cache_path: a JSON file {"erx_tune": 1, "entries": [...]} that is read first (an entry
- * for the same bands, pixels, dtype, precision, fp64_cond_threshold, normalise and
- * nstreams is returned without timing) and updated with a new result, or NULL.  Uses the
+ * for the same bands, pixels, dtype, precision, fp64_cond_threshold, normalise, score_arith,
+ * state_fp32 and nstreams is returned without timing) and updated with a new result, or NULL.  Uses the
  * current HIP device and allocates the synthetic input (at most 4 GiB) for the duration
  * of the call.  ERX_EINVAL for invalid arguments or an unreadable cache file (nothing is
  * timed), ERX_ENOMEM / ERX_EDEVICE on device failures. */

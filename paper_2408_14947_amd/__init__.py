@@ -561,13 +561,16 @@ __all__ = ["Detector", "Batch", "RXBaseline", "detection_metrics", "srp_matrix",
 PARAM_ORDER = ("W", "c", "A1", "a1", "w2", "c2")
 
 
-def _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise):
+def _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise,
+                 score_arith="split16", state_fp32=False):
     cfg = Config()
     load().erx_config_default(C.byref(cfg), int(bands), int(pixels), float(momentum))
     cfg.dtype = DTYPES[dtype]
     cfg.precision = PRECISIONS[precision]
     cfg.fp64_cond_threshold = float(fp64_cond_threshold)
     cfg.normalise = 1 if normalise else 0
+    cfg.score_arith = SCORE_ARITH[score_arith]
+    cfg.state_fp32 = 1 if state_fp32 else 0
     return cfg
 
 
@@ -578,12 +581,13 @@ def _tune_dict(r):
 
 def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32", precision: str = "split16",
              fp64_cond_threshold: float = 0.0, normalise: bool = False, nstreams: int = 1,
-             cache: Optional[str] = None) -> dict:
+             cache: Optional[str] = None, score_arith: str = "split16", state_fp32: bool = False) -> dict:
     """Fastest launch setting for a workload shape (erx_autotune): block_lines, scan_lines,
     small_path (batch mode, -1 for one stream), score_tiles (the score kernel's tile shape),
     candidates timed, us_per_line."""
     lib = load()
-    cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise)
+    cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise, score_arith,
+                       state_fp32)
     r = TuneResult()
     _check(lib.erx_autotune(C.byref(cfg), int(nstreams), cache.encode() if cache else None, C.byref(r)))
     return _tune_dict(r)
@@ -591,10 +595,11 @@ def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32",
 
 def tune_lookup(bands: int, pixels: int, cache: str, momentum: float = 0.1, dtype: str = "f32",
                 precision: str = "split16", fp64_cond_threshold: float = 0.0, normalise: bool = False,
-                nstreams: int = 1) -> Optional[dict]:
+                nstreams: int = 1, score_arith: str = "split16", state_fp32: bool = False) -> Optional[dict]:
     """Cached setting for a workload shape (erx_tune_lookup), or None when the cache has none."""
     lib = load()
-    cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise)
+    cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise, score_arith,
+                       state_fp32)
     r = TuneResult()
     rc = _check(lib.erx_tune_lookup(C.byref(cfg), int(nstreams), cache.encode(), C.byref(r)), allow=(ERX_ESTATE,))
     return None if rc == ERX_ESTATE else _tune_dict(r)

@@ -51,17 +51,20 @@ __global__ __launch_bounds__(256) void k_tune_fill(void* X, long long n, int dty
 struct Key {
     int bands, pixels, dtype, precision, normalise, nstreams;
     double thr;
+    int score_arith, state_fp32;  // entries written before these were keyed read as 0 (the defaults then)
 };
 
 Key key_of(const erx_config& c, int nstreams)
 {
-    return Key{c.bands, c.pixels, c.dtype, c.precision, c.normalise, nstreams, c.fp64_cond_threshold};
+    return Key{c.bands, c.pixels, c.dtype, c.precision, c.normalise, nstreams, c.fp64_cond_threshold,
+               c.score_arith, c.state_fp32};
 }
 
 bool same(const Key& a, const Key& b)
 {
     return a.bands == b.bands && a.pixels == b.pixels && a.dtype == b.dtype && a.precision == b.precision &&
-           a.normalise == b.normalise && a.nstreams == b.nstreams && a.thr == b.thr;
+           a.normalise == b.normalise && a.nstreams == b.nstreams && a.thr == b.thr &&
+           a.score_arith == b.score_arith && a.state_fp32 == b.state_fp32;
 }
 
 struct Entry {
@@ -132,7 +135,10 @@ std::vector<Entry> load_cache(const char* path, bool* bad)
                 return out;
             }
         Entry e{};
-        e.k = Key{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], v[6]};
+        double sa = 0.0, s32 = 0.0;
+        (void)field(obj, "score_arith", &sa);
+        (void)field(obj, "state_fp32", &s32);
+        e.k = Key{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], v[6], (int)sa, (int)s32};
         e.r.block_lines = (int)v[7];
         e.r.scan_lines = (int)v[8];
         e.r.small_path = (int)v[9];
@@ -156,9 +162,11 @@ bool save_cache(const char* path, const std::vector<Entry>& es)
         const Entry& e = es[i];
         std::fprintf(f,
                      "  {\"bands\": %d, \"pixels\": %d, \"dtype\": %d, \"precision\": %d, \"normalise\": %d, "
-                     "\"nstreams\": %d, \"fp64_cond_threshold\": %.17g, \"block_lines\": %d, \"scan_lines\": %d, "
+                     "\"nstreams\": %d, \"fp64_cond_threshold\": %.17g, \"score_arith\": %d, \"state_fp32\": %d, "
+                     "\"block_lines\": %d, \"scan_lines\": %d, "
                      "\"small_path\": %d, \"score_tiles\": %d, \"us_per_line\": %.6g}%s\n",
                      e.k.bands, e.k.pixels, e.k.dtype, e.k.precision, e.k.normalise, e.k.nstreams, e.k.thr,
+                     e.k.score_arith, e.k.state_fp32,
                      e.r.block_lines, e.r.scan_lines, e.r.small_path, e.r.score_tiles, e.r.us_per_line,
                      i + 1 < es.size() ? "," : "");
     }

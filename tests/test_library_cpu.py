@@ -119,6 +119,9 @@ def test_tune_cache_lookup(tmp_path):
     r = erx.tune_lookup(224, 1024, path)
     assert r == {"block_lines": 4096, "scan_lines": 32, "small_path": -1, "score_tiles": 0, "candidates": 0,
                  "us_per_line": 11.5}
+    # the arithmetic is part of the key (entries without it were written for the defaults)
+    assert erx.tune_lookup(224, 1024, path, score_arith="fp32") is None
+    assert erx.tune_lookup(224, 1024, path, state_fp32=True) is None
     r = erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1024)
     assert r["small_path"] == 1 and r["block_lines"] == 1024
     assert erx.tune_lookup(8, 1280, path, dtype="f16", nstreams=1) is None        # other stream count
