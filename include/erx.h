@@ -121,6 +121,10 @@ typedef struct erx_config {
     int score_tiles;   /* tile shape of the split-FP16 score kernel: 16-pixel tiles per wave, 1 or 2;
                           0 (default): 1 above 192 bands (where two would spill registers), else 2.
                           Results do not depend on it; erx_autotune chooses it */
+    int gram_macro;    /* bands per macro tile (one workgroup's block of the Gram) of the split-FP16
+                          Gram: 64 or 128; 0 (default): 128 from 65 bands on, else 64.  128-band
+                          macro tiles split each element into its FP16 halves half as often at
+                          224 bands.  Results do not depend on it (both write the same values) */
 } erx_config;
 
 enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };

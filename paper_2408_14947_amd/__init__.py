@@ -56,7 +56,7 @@ class Config(C.Structure):
                 ("normalise", C.c_int), ("block_lines", C.c_int), ("scan_lines", C.c_int),
                 ("cond_estimate", C.c_int), ("score_arith", C.c_int), ("srp_dims", C.c_int),
                 ("srp_seed", C.c_ulonglong), ("background", C.c_int), ("state_fp32", C.c_int),
-                ("score_tiles", C.c_int)]
+                ("score_tiles", C.c_int), ("gram_macro", C.c_int)]
 
 
 class DetectionMetrics(C.Structure):
@@ -196,7 +196,8 @@ class Detector:
                  normalise: bool = False, warmup: int = 0, block_lines: int = 2048,
                  scan_lines: int = 64, cond_estimate: int = -1, stream: Optional[int] = -1,
                  score_arith: str = "split16", srp_dims: int = 0, srp_seed: int = 0,
-                 background: str = "ema", state_fp32: bool = False, score_tiles: int = 0):
+                 background: str = "ema", state_fp32: bool = False, score_tiles: int = 0,
+                 gram_macro: int = 0):
         """stream: hipStream_t handle to run on; -1 (default) = torch's current
         stream, None = a stream owned by the handle.  srp_dims > 0: project every line
         to that many dimensions first (Sec. III-B, weights from srp_matrix).
@@ -219,6 +220,7 @@ class Detector:
         cfg.background = BACKGROUNDS[background]
         cfg.state_fp32 = 1 if state_fp32 else 0
         cfg.score_tiles = int(score_tiles)
+        cfg.gram_macro = int(gram_macro)
         self.cfg = cfg
         self.bands, self.pixels, self.dtype = int(bands), int(pixels), dtype
         self.work_bands = int(srp_dims) if srp_dims else int(bands)
@@ -344,7 +346,7 @@ class Batch:
                  fp64_cond_threshold: float = 0.0, normalise: bool = False, block_lines: int = 8192,
                  scan_lines: int = 64, cond_estimate: int = -1, graphs: bool = True, score_arith: str = "split16",
                  stream: Optional[int] = -1, small_path: int = -1, state_fp32: bool = False,
-                 score_tiles: int = 0):
+                 score_tiles: int = 0, gram_macro: int = 0):
         lib = load()
         self.bands = [int(x) for x in bands]
         self.pixels = [int(x) for x in pixels]
@@ -364,6 +366,7 @@ class Batch:
         cfg.score_arith = SCORE_ARITH[score_arith]
         cfg.state_fp32 = 1 if state_fp32 else 0
         cfg.score_tiles = int(score_tiles)
+        cfg.gram_macro = int(gram_macro)
         b = (C.c_int * ns)(*self.bands)
         p = (C.c_int * ns)(*self.pixels)
         m = (C.c_float * ns)(*[float(x) for x in momentum])

@@ -24,7 +24,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["erx_kernels.hip", "erx_small.hip", "erx_api.hip", "erx_runtime.hip", "erx_batch.hip", "erx_surr.hip", "erx_tune.hip", "erx_noalloc.hip", "erx_score16.hip", "erx_metrics.hip", "erx_srp.hip", "erx_rxb.hip"]
+SOURCES = ["erx_kernels.hip", "erx_small.hip", "erx_api.hip", "erx_runtime.hip", "erx_batch.hip", "erx_surr.hip", "erx_tune.hip", "erx_noalloc.hip", "erx_score16.hip", "erx_metrics.hip", "erx_srp.hip", "erx_rxb.hip", "erx_gram8.hip"]
 
 
 def _compile(src: str) -> str:

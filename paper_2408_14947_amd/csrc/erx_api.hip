@@ -220,6 +220,10 @@ erx_ctx* erx_create_ex(const erx_config* cfg)
         fail(ERX_EINVAL, "background must be ERX_BG_EMA or ERX_BG_IMC, got %d", c.background);
         return nullptr;
     }
+    if (c.gram_macro != 0 && c.gram_macro != 64 && c.gram_macro != 128) {
+        fail(ERX_EINVAL, "gram_macro must be 0, 64 or 128, got %d", c.gram_macro);
+        return nullptr;
+    }
     if (c.score_tiles < 0 || c.score_tiles > 2) {
         fail(ERX_EINVAL, "score_tiles must be 0, 1 or 2, got %d", c.score_tiles);
         return nullptr;
@@ -374,6 +378,7 @@ int erx_push_lines_ex(erx_ctx* h, const void* lines, int n)
         P.gredo = h->gredo;
         P.sf32 = c.state_fp32;
         P.spt = c.score_tiles;
+        P.gmacro = c.gram_macro;
         HIPCHK(run_pass(h->stream, P, h->NT, pdt, c.precision, c.score_arith, h->stats, h->carry, h->Mt, h->mu32, h->flags + c0,
                         h->cond + c0, thr, want_cond, fp64_pass, c.normalise != 0, h->ctr,
                         h->profile ? &h->prof : nullptr));

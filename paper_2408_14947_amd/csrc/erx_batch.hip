@@ -145,7 +145,7 @@ erx_batch* erx_batch_create(int nstreams, const int* bands, const int* pixels, c
         c.cond_estimate < -1 || c.cond_estimate > 1 || (c.normalise != 0 && c.normalise != 1) ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
         c.background != ERX_BG_EMA || (c.state_fp32 != 0 && c.state_fp32 != 1) || c.score_tiles < 0 ||
-        c.score_tiles > 2) {
+        c.score_tiles > 2 || (c.gram_macro != 0 && c.gram_macro != 64 && c.gram_macro != 128)) {
         fail(ERX_EINVAL, "erx_batch_create: invalid common configuration");
         return nullptr;
     }
@@ -424,6 +424,7 @@ int erx_batch_push(erx_batch* bt, const void* const* lines, const int* nlines)
                 P.gredo = g.gredo;
                 P.sf32 = c.state_fp32;
                 P.spt = c.score_tiles;
+                P.gmacro = c.gram_macro;
                 auto record = [&]() -> hipError_t {
                     hipError_t e = hipMemcpyAsync(g.d_sd[slot], hd, nsd * sizeof(StreamDesc), hipMemcpyHostToDevice,
                                                   gstream);

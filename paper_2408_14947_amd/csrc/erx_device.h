@@ -42,6 +42,18 @@ __device__ __forceinline__ float absmax4(const f4 v)
     return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
 }
 
+// Split-FP16 Gram operands: the power of two c with m c in [2^7, 2^8), so that
+// values up to 128 m stay below 2^15 after scaling (1 when m is 0 or not
+// finite), and 1 / c
+__device__ __forceinline__ void split_scale(float m, float& c, float& inv)
+{
+    int E = ((__float_as_int(m) >> 23) & 0xff) - 127;
+    const bool ok = m > 0.f && E < 128;
+    E = E < -119 ? -119 : (E > 120 ? 120 : E);
+    c = ok ? __int_as_float((127 + 7 - E) << 23) : 1.f;
+    inv = ok ? __int_as_float((127 - 7 + E) << 23) : 1.f;
+}
+
 // acc += X^T Y for two accumulator-layout tiles held as register quadruples
 template <class V>
 __device__ __forceinline__ V mma_xty(V acc, const V x, const V y)

@@ -59,11 +59,15 @@ struct Pass {
                            // averaging itself still runs in FP64); 0: FP64 storage
     int spt;               // 16-pixel tiles per wave of the split-FP16 score kernel: 1, 2, or 0
                            // for 1 from 13 band tiles on and SCORE_PT below
+    int gmacro;            // bands per macro tile of the split-FP16 Gram: 64 (k_gram4), 128
+                           // (k_gram8), or 0 for 128 from 5 band tiles on and 64 below
 };
 constexpr int GRAM_MACROS_MAX = 15;  // upper 64x64 macro tiles of a 304-band Gram
 
 // stats / carry: FP64 or (P.sf32) FP32 arrays of stat_entries(NT) values per line / segment
 hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, void* stats, hipStream_t s);
+// split-FP16 Gram on 128-band macro tiles; nm = upper 64-band macro tiles (the Pass::gredo stride)
+hipError_t launch_gram8(int dtype, const Pass& P, int NT, int nm, void* stats, long long E, hipStream_t s);
 hipError_t launch_scan_local(const Pass& P, int NT, void* stats, hipStream_t s);
 // IMC: per-line statistics (K_hat, mu_hat) -> second moments about the stream's reference mean
 // (FP64 storage only)

@@ -299,17 +299,6 @@ template <> struct G4<ERX_GRAM_SPLIT16> {
     }
 };
 
-// power of two c with m c in [2^7, 2^8), so that values up to 128 m stay below
-// 2^15 after scaling (1 when m is 0 or not finite), and 1 / c
-__device__ __forceinline__ void split_scale(float m, float& c, float& inv)
-{
-    int E = ((__float_as_int(m) >> 23) & 0xff) - 127;
-    const bool ok = m > 0.f && E < 128;
-    E = E < -119 ? -119 : (E > 120 ? 120 : E);
-    c = ok ? __int_as_float((127 + 7 - E) << 23) : 1.f;
-    inv = ok ? __int_as_float((127 - 7 + E) << 23) : 1.f;
-}
-
 // The part of a macro tile's work that depends on whether it is diagonal (one
 // panel, rows = columns) is compiled separately for both cases, so that no
 // load sits under a branch.
@@ -1463,7 +1452,8 @@ hipError_t launch_gram(int dtype, int prec, const Pass& P, int NT, void* stats, 
     else if (prec == ERX_GRAM_FP16) launch_gram4<ERX_GRAM_FP16>(dtype, grid, block, s, P, NT, nm, stats, E);
     else if (prec == ERX_GRAM_SPLIT16 && P.gredo) {
         // split FP16, then FP32 for the macro tiles it flagged (the others return at once)
-        launch_gram4<ERX_GRAM_SPLIT16>(dtype, grid, block, s, P, NT, nm, stats, E);
+        if (P.gmacro == 128 || (P.gmacro == 0 && NT >= 5)) launch_gram8(dtype, P, NT, nm, stats, E, s);
+        else launch_gram4<ERX_GRAM_SPLIT16>(dtype, grid, block, s, P, NT, nm, stats, E);
         launch_gram4<ERX_GRAM_FP32>(dtype, grid, block, s, P, NT, nm, stats, E, P.gredo);
     } else launch_gram4<ERX_GRAM_FP32>(dtype, grid, block, s, P, NT, nm, stats, E);
     return hipGetLastError();

@@ -113,6 +113,8 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
     if (c.background != ERX_BG_EMA) return set_error(ERX_EINVAL, "erx_push_lines_noalloc runs the moving averages (background must be ERX_BG_EMA)");
     if (c.state_fp32 != 0) return set_error(ERX_EINVAL, "erx_push_lines_noalloc keeps an FP64 state (state_fp32 must be 0)");
     if (c.score_tiles < 0 || c.score_tiles > 2) return set_error(ERX_EINVAL, "score_tiles must be 0, 1 or 2");
+    if (c.gram_macro != 0 && c.gram_macro != 64 && c.gram_macro != 128)
+        return set_error(ERX_EINVAL, "gram_macro must be 0, 64 or 128");
     if (c.block_lines < 1 || c.scan_lines < 1) return set_error(ERX_EINVAL, "block_lines and scan_lines must be >= 1");
     if (n < 1) return set_error(ERX_EINVAL, "n must be >= 1, got %d", n);
     if (t0 < 0) return set_error(ERX_EINVAL, "t0 must be >= 0");
@@ -199,6 +201,7 @@ int erx_push_lines_noalloc(const erx_config* cfg, double* state, long long t0, c
         P.vec4 = (c.bands % 4) == 0 && ((uintptr_t)src % (4 * esz)) == 0;
         P.mscale = mscale;
         P.spt = c.score_tiles;
+        P.gmacro = c.gram_macro;
         P.gredo = gredo;
         e = run_pass(s, P, NT, c.dtype, c.precision, c.score_arith, stats, carry, Mt, mu32, flags, cond, thr, want_cond, fp64_pass,
                      false, ctr, nullptr);

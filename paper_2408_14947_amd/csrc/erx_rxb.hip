@@ -181,7 +181,7 @@ erx_rxb* erx_rxb_create(const erx_config* cfg, int window)
         !(c.fp64_cond_threshold >= 0.0) || c.block_lines < 1 || c.scan_lines < 1 ||
         (c.score_arith != ERX_SCORE_SPLIT16 && c.score_arith != ERX_SCORE_FP32) || c.srp_dims != 0 ||
         c.normalise != 0 || c.cond_estimate < -1 || c.cond_estimate > 1 || c.state_fp32 != 0 || c.score_tiles < 0 ||
-        c.score_tiles > 2) {
+        c.score_tiles > 2 || (c.gram_macro != 0 && c.gram_macro != 64 && c.gram_macro != 128)) {
         set_error(ERX_EINVAL, "erx_rxb_create: invalid configuration (bands in [1, %d], pixels >= 2, ridge >= 0, "
                               "no projection, no normalisation, FP64 state)", ERX_MAX_BANDS);
         return nullptr;
@@ -316,6 +316,7 @@ int erx_rxb_push(erx_rxb* r, const void* lines, int n)
             Q.vec4 = (c.bands % 4) == 0 && ((uintptr_t)Q.one.x % (4 * esz)) == 0;
             Q.mscale = r->mscale;
             Q.spt = c.score_tiles;
+            Q.gmacro = c.gram_macro;
             hipError_t e;
             if (thr > 0.0) {
                 e = launch_chol(0, fp64_pass ? 0 : 1, Q, r->NT, r->fin, r->fin, r->Mt, r->mu32, r->flags, r->cond,

@@ -163,16 +163,18 @@ def test_split16_gram_parity(erx, b, p, T):
     assert err.max() <= 1e-4
 
 
-def test_split16_gram_redo_paths(erx):
+@pytest.mark.parametrize("gram_macro", [64, 128])
+def test_split16_gram_redo_paths(erx, gram_macro):
     """Blocks the split cannot hold are recomputed in FP32: a band constant over the first
-    64 pixels of a line, and a later pixel 1000 times the first chunk's spread."""
-    log("split-FP16 Gram: FP32 redo of flagged blocks")
+    64 pixels of a line, and a later pixel 1000 times the first chunk's spread (with
+    either macro tile size: a 128-band macro tile flags the 64-band ones it covers)."""
+    log(f"split-FP16 Gram: FP32 redo of flagged blocks, {gram_macro}-band macro tiles")
     rng = np.random.default_rng(62)
     T, p, b = 8, 200, 70
     X = (0.5 + 0.02 * rng.standard_normal((T, p, b))).astype(np.float32)
     X[2, :64, 5] = 0.25          # constant over the first chunk of line 2
     X[5, 150, 40] += 30.0        # far beyond the first chunk's spread in line 5
-    det = erx.Detector(b, p, 0.1, precision="split16")
+    det = erx.Detector(b, p, 0.1, precision="split16", gram_macro=gram_macro)
     det.push(torch.from_numpy(X).cuda())
     got = det.scores().cpu().numpy()
     want = oracle.run(X, 0.1, 1e-5)["delta"]

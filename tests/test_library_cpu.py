@@ -44,7 +44,8 @@ def test_library_exports_every_declared_symbol():
                                          ("momentum", float("nan")), ("ridge", -1e-3),
                                          ("dtype", 7), ("precision", 4), ("block_lines", 0), ("scan_lines", 0),
                                          ("warmup", -1), ("fp64_cond_threshold", -1.0),
-                                         ("cond_estimate", 2), ("state_fp32", 2), ("score_tiles", 3)])
+                                         ("cond_estimate", 2), ("state_fp32", 2), ("score_tiles", 3),
+                                         ("gram_macro", 96)])
 def test_create_rejects_invalid_config(field, value):
     erx, lib = _lib()
     cfg = erx.Config()
@@ -82,7 +83,7 @@ def test_config_layout_matches_the_header():
     lib.erx_config_default(C.cast(buf, C.POINTER(erx.Config)), 8, 16, 0.1)
     assert all(v == 0xAB for v in buf[n:])
     cfg = erx.Config.from_buffer_copy(bytes(buf[:n]))
-    assert cfg.state_fp32 == 0 and cfg.bands == 8
+    assert cfg.state_fp32 == 0 and cfg.gram_macro == 0 and cfg.bands == 8
 
 
 def test_state_fp32_combinations_rejected():
