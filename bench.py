@@ -24,7 +24,7 @@ METRIC = "ERX pixels/s + lines/s at 108/224 bands; mixed/batched vs plain FP32 a
 PEAK = {"fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 # sources of the kernels the long-scan workload runs (the traffic record is tied to them)
 KERNEL_SRC = [os.path.join(ROOT, "paper_2408_14947_amd", "csrc", f)
-              for f in ("erx_kernels.hip", "erx_device.h", "erx_score16.hip")]
+              for f in ("erx_kernels.hip", "erx_device.h", "erx_score16.hip", "erx_gram8.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_long-scan-224.md")
 WORKLOAD = ("long-scan-224: one stream, 20000 lines x 1024 px x 224 bands, f32, momentum 0.1, "
             "ridge 1e-5, drifting 4-endmember mixture, 0.2% 3x3 patches")
@@ -40,7 +40,7 @@ def kernel_source_hash():
 
 def short_kernel(name):
     """Map a device kernel's demangled name to the short name the library's profiler uses."""
-    m = re.search(r"erx::k_(\w+?)(<([^>]*)>)?\(", name)
+    m = re.search(r"erx::(?:\(anonymous namespace\)::)?k_(\w+?)(<([^>]*)>)?\(", name)
     if not m:
         return None
     k = m.group(1)
@@ -51,7 +51,7 @@ def short_kernel(name):
         return "gram_fp32" if len(args) > 1 and args[1] == "0" else "gram"
     # the library's profiler names: the split-FP16 score kernel is "score", the FP32 one runs
     # after it for the lines it flags
-    return {"gram4": "gram", "score16": "score", "score": "score_fp32_redo"}.get(k, k)
+    return {"gram4": "gram", "gram8": "gram", "score16": "score", "score": "score_fp32_redo"}.get(k, k)
 
 
 def _csv_rows(d, suffix):
@@ -80,7 +80,7 @@ def summarize_trace(d, command, workload=WORKLOAD):
         if k is None:
             return name[:60] + ("..." if len(name) > 60 else "")
         if k in dup:
-            m = re.search(r"erx::k_\w+?<([^>]*)>", name)
+            m = re.search(r"erx::(?:\(anonymous namespace\)::)?k_\w+?<([^>]*)>", name)
             return f"{k}<{m.group(1).replace(' ', '')}>" if m else k
         return k
 

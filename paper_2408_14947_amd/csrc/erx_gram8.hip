@@ -47,12 +47,9 @@ constexpr int G8_PLANE = G8_B * 64;  // halves per plane: 128 band rows x 64 pix
 
 __device__ __forceinline__ int g8_sw(int r) { return (r >> 1) & 7; }
 
-// the FP16 halves of pixels 4pq..4pq+3 of band row r, v scaled by sc
-__device__ __forceinline__ void g8_put(uint16_t* H, int r, int pq, const f4 v, float sc)
+// the FP16 halves of the scaled values w4 of pixels 4pq..4pq+3 of band row r
+__device__ __forceinline__ void g8_put(uint16_t* H, int r, int pq, const f4 w4)
 {
-    f4 w4;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) w4[q] = v[q] * sc;
     const g8h4 hi = __builtin_convertvector(w4, g8h4);
     const f4 back = __builtin_convertvector(hi, f4);
     f4 d4;
@@ -184,26 +181,31 @@ __device__ __forceinline__ void gram8_macro(const void* X, int p, int b, int NT,
         split_scale(m, cv, ci);
         scl_s[tid] = cv;
         scl_s[256 + tid] = ci;
+        scl_s[512 + tid] = -(shift_s[tid] * cv);  // exact: c is a power of two
         if (band < b && !(m > 0.f)) *redo_s = 1;  // constant over the first chunk (or NaN)
     }
     __syncthreads();
 
+    // (x - s) c is formed as one FMA, x c + (-s c): c is a power of two, so this is
+    // the rounded x - s scaled exactly, the value k_gram4 forms in two steps.  The
+    // band sums are kept in that scale (exactly c times the unscaled sums) and
+    // unscaled when they are added into FP64.
     bool ovf = false;
     auto stage = [&](int k0, int buf, const f4(&fr)[4]) __attribute__((always_inline)) {
         if (!stager) return;
         uint16_t* H = pl[buf][pn];
         const int nv = p - k0 - 4 * pq;  // valid pixels among this lane's four
-        // shifts and scales are read back from LDS, which keeps registers for the tiles
-        const f4 sh = *(const f4*)&shift_s[pn * 128 + pr];
+        // scales and shifts are read back from LDS, which keeps registers for the tiles
         const f4 cs = *(const f4*)&scl_s[pn * 128 + pr];
+        const f4 ns = *(const f4*)&scl_s[512 + pn * 128 + pr];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             f4 x;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) x[r] = (r < nv && bok[j]) ? fr[r][j] - sh[j] : 0.f;
+            for (int r = 0; r < 4; ++r) x[r] = (r < nv && bok[j]) ? fmaf(fr[r][j], cs[j], ns[j]) : 0.f;
             sr[j] += (x[0] + x[1]) + (x[2] + x[3]);
-            ovf = ovf || absmax4(x) * cs[j] >= 32768.f;
-            g8_put(H, pr + j, pq, x, cs[j]);
+            ovf = ovf || absmax4(x) >= 32768.f;
+            g8_put(H, pr + j, pq, x);
         }
     };
 
@@ -253,10 +255,13 @@ __device__ __forceinline__ void gram8_macro(const void* X, int p, int b, int NT,
             }
             acc[q] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        if (stager) {  // band sums of the chunks staged so far, unscaled
+            const f4 ci = *(const f4*)&scl_s[256 + pn * 128 + pr];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {  // band sums of the chunks staged so far
-            dsr[j] += (double)sr[j];
-            sr[j] = 0.f;
+            for (int j = 0; j < 4; ++j) {
+                dsr[j] += (double)sr[j] * (double)ci[j];
+                sr[j] = 0.f;
+            }
         }
         if (k0 + 64 >= p) break;
         stage(k0 + 64, (it + 1) & 1, fs);
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(1024) void k_gram8(const Pass P, int NT, int nm8, i
     const int MJ = MI + m;
     __shared__ __attribute__((aligned(16))) uint16_t pl[2][2][2 * G8_PLANE];  // [buffer][panel][hi, lo]
     __shared__ float shift_s[256];  // row panel bands, then column panel bands
-    __shared__ float scl_s[512];    // scales (rows, columns), then their inverses
+    __shared__ float scl_s[768];    // scales (rows, columns), their inverses, then -shift * scale
     __shared__ double bsum_s[256];
     __shared__ int redo_s;
     if (MI == MJ)
