@@ -236,7 +236,8 @@ def tune_leg(erx, torch, X, b, p, momentum, args, stream, ms_default):
         res["multispectral_batch_b16"] = dict(rb, tuning_s=time.perf_counter() - t0)
     torch.cuda.empty_cache()
     ms, _, _, _ = time_workload(erx, torch, X, b, p, momentum, args.steps, 1, r["block_lines"], stream,
-                                profile=False, scan_lines=r["scan_lines"], score_tiles=r["score_tiles"])
+                                profile=False, scan_lines=r["scan_lines"], score_tiles=r["score_tiles"],
+                                gram_macro=r["gram_macro"])
     res["long_scan"]["ms_per_step_tuned"] = ms / args.steps
     res["long_scan"]["ms_per_step_default"] = ms_default
     return res

@@ -261,9 +261,10 @@ ERX_API void erx_batch_destroy(erx_batch *bt);
  * lines per device pass (block_lines 512..8192) x scan segment (scan_lines 32, 64, 128);
  * for a batch, pass capacity (1024, 4096, 16384) and, when bands <= 16, the small-band
  * path mode (erx_batch_small_path 0, 1, 2); with the split-FP16 score, each also x the
- * score kernel's tile shape (score_tiles 1, 2).  No candidate changes what is computed:
+ * score kernel's tile shape (score_tiles 1, 2); with the split-FP16 Gram above 64 bands,
+ * each also x the Gram's macro tile (gram_macro 64, 128).  No candidate changes what is computed:
  * pass and segment lengths only regroup the FP64 moving-average updates (scores agree with
- * an untuned handle's to 1e-6 relative), the tile shape changes no product, and the
+ * an untuned handle's to 1e-6 relative), the tile shapes change no product, and the
  * small-band modes agree with the general path as erx_batch_small_path states.  The timings are those of well-conditioned
  * backgrounds (no FP64 re-factor triggered).
  * ------------------------------------------------------------------------------------- */
@@ -274,6 +275,7 @@ typedef struct erx_tune_result {
     int candidates;     /* settings timed by this call; 0 when the result came from the cache */
     double us_per_line; /* measured microseconds per line (per stream line for a batch) */
     int score_tiles;    /* erx_config.score_tiles to use */
+    int gram_macro;     /* erx_config.gram_macro to use */
 } erx_tune_result;
 /* cfg: the workload (its block_lines and scan_lines are ignored); nstreams >= 1 (1: a
  * detector made with erx_create_ex, more: a batch of that many streams of cfg's shape);

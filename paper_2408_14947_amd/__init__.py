@@ -67,7 +67,8 @@ class DetectionMetrics(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("block_lines", C.c_int), ("scan_lines", C.c_int), ("small_path", C.c_int),
-                ("candidates", C.c_int), ("us_per_line", C.c_double), ("score_tiles", C.c_int)]
+                ("candidates", C.c_int), ("us_per_line", C.c_double), ("score_tiles", C.c_int),
+                ("gram_macro", C.c_int)]
 
 
 class KernelTime(C.Structure):
@@ -579,7 +580,8 @@ def _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold,
 
 def _tune_dict(r):
     return {"block_lines": r.block_lines, "scan_lines": r.scan_lines, "small_path": r.small_path,
-            "score_tiles": r.score_tiles, "candidates": r.candidates, "us_per_line": r.us_per_line}
+            "score_tiles": r.score_tiles, "gram_macro": r.gram_macro, "candidates": r.candidates,
+            "us_per_line": r.us_per_line}
 
 
 def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32", precision: str = "split16",
@@ -587,6 +589,7 @@ def autotune(bands: int, pixels: int, momentum: float = 0.1, dtype: str = "f32",
              cache: Optional[str] = None, score_arith: str = "split16", state_fp32: bool = False) -> dict:
     """Fastest launch setting for a workload shape (erx_autotune): block_lines, scan_lines,
     small_path (batch mode, -1 for one stream), score_tiles (the score kernel's tile shape),
+    gram_macro (the split-FP16 Gram's macro tile),
     candidates timed, us_per_line."""
     lib = load()
     cfg = _tune_config(bands, pixels, momentum, dtype, precision, fp64_cond_threshold, normalise, score_arith,

@@ -143,8 +143,9 @@ std::vector<Entry> load_cache(const char* path, bool* bad)
         e.r.scan_lines = (int)v[8];
         e.r.small_path = (int)v[9];
         e.r.us_per_line = v[10];
-        double st = 0.0;  // entries written before the score tile shape was tuned: the default
+        double st = 0.0, gm = 0.0;  // entries written before these were tuned: the defaults
         e.r.score_tiles = field(obj, "score_tiles", &st) ? (int)st : 0;
+        e.r.gram_macro = field(obj, "gram_macro", &gm) ? (int)gm : 0;
         e.r.candidates = 0;
         out.push_back(e);
         i = b;
@@ -164,10 +165,10 @@ bool save_cache(const char* path, const std::vector<Entry>& es)
                      "  {\"bands\": %d, \"pixels\": %d, \"dtype\": %d, \"precision\": %d, \"normalise\": %d, "
                      "\"nstreams\": %d, \"fp64_cond_threshold\": %.17g, \"score_arith\": %d, \"state_fp32\": %d, "
                      "\"block_lines\": %d, \"scan_lines\": %d, "
-                     "\"small_path\": %d, \"score_tiles\": %d, \"us_per_line\": %.6g}%s\n",
+                     "\"small_path\": %d, \"score_tiles\": %d, \"gram_macro\": %d, \"us_per_line\": %.6g}%s\n",
                      e.k.bands, e.k.pixels, e.k.dtype, e.k.precision, e.k.normalise, e.k.nstreams, e.k.thr,
                      e.k.score_arith, e.k.state_fp32,
-                     e.r.block_lines, e.r.scan_lines, e.r.small_path, e.r.score_tiles, e.r.us_per_line,
+                     e.r.block_lines, e.r.scan_lines, e.r.small_path, e.r.score_tiles, e.r.gram_macro, e.r.us_per_line,
                      i + 1 < es.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
@@ -201,12 +202,13 @@ struct Bench {
 
 // milliseconds of one push of n lines by a single detector with the given
 // setting (after a warm-up push), or a negative value with the error set
-double time_single(const erx_config& base, int B, int S, int pt, Bench& bn, int n)
+double time_single(const erx_config& base, int B, int S, int pt, int gm, Bench& bn, int n)
 {
     erx_config c = base;
     c.block_lines = B;
     c.scan_lines = S;
     c.score_tiles = pt;
+    c.gram_macro = gm;
     erx_ctx* h = erx_create_ex(&c);
     if (!h) return -1.0;
     double ms = -1.0;
@@ -221,11 +223,12 @@ double time_single(const erx_config& base, int B, int S, int pt, Bench& bn, int 
 }
 
 // milliseconds of one push of T lines to each of ns identical streams of a batch
-double time_batch(const erx_config& base, int ns, int B, int mode, int pt, Bench& bn, int T)
+double time_batch(const erx_config& base, int ns, int B, int mode, int pt, int gm, Bench& bn, int T)
 {
     erx_config c = base;
     c.block_lines = B;
     c.score_tiles = pt;
+    c.gram_macro = gm;
     std::vector<int> bands(ns, base.bands), pixels(ns, base.pixels), nl(ns, T);
     std::vector<float> mom(ns, base.momentum);
     erx_batch* bt = erx_batch_create(ns, bands.data(), pixels.data(), mom.data(), &c);
@@ -311,31 +314,39 @@ int erx_autotune(const erx_config* cfg, int nstreams, const char* cache_path, er
     // the score tile shapes matter only to the split-FP16 score kernel
     std::vector<int> pts = {2};
     if (cfg->score_arith == ERX_SCORE_SPLIT16) pts = {1, 2};
+    // and the Gram's blocking only to the split-FP16 Gram, with more than one 64-band macro tile
+    std::vector<int> gms = {0};
+    if (cfg->precision == ERX_GRAM_SPLIT16 && cfg->bands > 64) gms = {64, 128};
     if (nstreams == 1) {
         for (int B : {512, 1024, 2048, 4096, 8192}) {
             if (B > n && B != 512) continue;
             for (int S : {32, 64, 128})
-                for (int pt : pts) {
-                    const double ms = time_single(*cfg, B, S, pt, bn, n);
-                    if (ms < 0.0) return ERX_EDEVICE;
-                    ++timed;
-                    const double us = ms * 1e3 / n;
-                    if (best.us_per_line < 0.0 || us < best.us_per_line) best = erx_tune_result{B, S, -1, 0, us, pt};
-                }
+                for (int pt : pts)
+                    for (int gm : gms) {
+                        const double ms = time_single(*cfg, B, S, pt, gm, bn, n);
+                        if (ms < 0.0) return ERX_EDEVICE;
+                        ++timed;
+                        const double us = ms * 1e3 / n;
+                        if (best.us_per_line < 0.0 || us < best.us_per_line)
+                            best = erx_tune_result{B, S, -1, 0, us, pt, gm};
+                    }
         }
     } else {
         std::vector<int> modes = {0};
         if (cfg->bands <= 16) modes = {0, 1, 2};
         for (int B : {1024, 4096, 16384})
             for (int mode : modes)
-                for (int pt : pts) {
-                    if (mode != 0 && (B != 1024 || pt != pts.back())) continue;  // the fused path cuts no passes and scores in its own kernel
-                    const double ms = time_batch(*cfg, nstreams, B, mode, pt, bn, T);
-                    if (ms < 0.0) return ERX_EDEVICE;
-                    ++timed;
-                    const double us = ms * 1e3 / ((double)T * nstreams);
-                    if (best.us_per_line < 0.0 || us < best.us_per_line) best = erx_tune_result{B, 64, mode, 0, us, pt};
-                }
+                for (int pt : pts)
+                    for (int gm : gms) {
+                        // the fused path cuts no passes and scores in its own kernel
+                        if (mode != 0 && (B != 1024 || pt != pts.back() || gm != gms.back())) continue;
+                        const double ms = time_batch(*cfg, nstreams, B, mode, pt, gm, bn, T);
+                        if (ms < 0.0) return ERX_EDEVICE;
+                        ++timed;
+                        const double us = ms * 1e3 / ((double)T * nstreams);
+                        if (best.us_per_line < 0.0 || us < best.us_per_line)
+                            best = erx_tune_result{B, 64, mode, 0, us, pt, gm};
+                    }
     }
     best.candidates = timed;
     *out = best;

@@ -34,11 +34,11 @@ def test_autotune_single_stream_caches_and_keeps_results(erx, tmp_path):
     r = erx.autotune(b, p, a, cache=cache)
     assert r["candidates"] > 0 and r["us_per_line"] > 0
     assert r["block_lines"] in (512, 1024, 2048, 4096, 8192) and r["scan_lines"] in (32, 64, 128)
-    assert r["score_tiles"] in (1, 2) and r["candidates"] == 5 * 3 * 2
+    assert r["score_tiles"] in (1, 2) and r["candidates"] == 5 * 3 * 2 and r["gram_macro"] == 0
     again = erx.autotune(b, p, a, cache=cache)
     assert again["candidates"] == 0
-    assert {k: again[k] for k in ("block_lines", "scan_lines", "small_path", "score_tiles")} == \
-        {k: r[k] for k in ("block_lines", "scan_lines", "small_path", "score_tiles")}
+    assert {k: again[k] for k in ("block_lines", "scan_lines", "small_path", "score_tiles", "gram_macro")} == \
+        {k: r[k] for k in ("block_lines", "scan_lines", "small_path", "score_tiles", "gram_macro")}
     assert erx.tune_lookup(b, p, cache)["block_lines"] == r["block_lines"]
     # scores of a handle with the tuned setting against the defaults, same lines
     sc = datagen.make_scene(2, 3, b, p, 300, drift=True, patches=True)
@@ -52,6 +52,16 @@ def test_autotune_single_stream_caches_and_keeps_results(erx, tmp_path):
         d.close()
     for o in outs[1:]:
         assert (np.abs(o - outs[0]) / np.maximum(np.abs(outs[0]), 1.0)).max() <= 1e-6
+
+
+def test_autotune_chooses_the_gram_blocking(erx, tmp_path):
+    """Above 64 bands the split-FP16 Gram's macro tile (64 or 128 bands) is a candidate too;
+    both write the same statistics, so the choice is a matter of time only."""
+    b, p = 108, 640
+    log(f"autotune one stream b={b} p={p} with the Gram blocking")
+    r = erx.autotune(b, p, 0.1, cache=str(tmp_path / "g.json"))
+    log(f"  {r}")
+    assert r["gram_macro"] in (64, 128) and r["candidates"] == 5 * 3 * 2 * 2
 
 
 def test_autotune_batch_of_small_band_streams(erx, tmp_path):

@@ -118,8 +118,8 @@ def test_tune_cache_lookup(tmp_path):
                 '"fp64_cond_threshold": 0, "block_lines": 1024, "scan_lines": 64, "small_path": 1, '
                 '"us_per_line": 0.04}\n]}\n')
     r = erx.tune_lookup(224, 1024, path)
-    assert r == {"block_lines": 4096, "scan_lines": 32, "small_path": -1, "score_tiles": 0, "candidates": 0,
-                 "us_per_line": 11.5}
+    assert r == {"block_lines": 4096, "scan_lines": 32, "small_path": -1, "score_tiles": 0, "gram_macro": 0,
+                 "candidates": 0, "us_per_line": 11.5}
     # the arithmetic is part of the key (entries without it were written for the defaults)
     assert erx.tune_lookup(224, 1024, path, score_arith="fp32") is None
     assert erx.tune_lookup(224, 1024, path, state_fp32=True) is None
