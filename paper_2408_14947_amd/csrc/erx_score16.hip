@@ -73,7 +73,7 @@ __device__ __forceinline__ HL split16(const f4 v, float s)
 // fewer accumulators per lane and more workgroups per line, two reuse each staged M tile
 // for twice the pixels)
 template <int NT, int DT, bool VEC, int PT>
-__global__ __launch_bounds__(256, PT == 1 ? (NT <= 13 ? 4 : 3) : (NT <= 14 ? 3 : 2)) void k_score16(const Pass P,
+__global__ __launch_bounds__(256, PT == 1 ? (NT <= 14 ? 4 : 3) : (NT <= 14 ? 3 : 2)) void k_score16(const Pass P,
                                                                                    const float* __restrict__ Mt,
                                                                     const float* __restrict__ mu32,
                                                                     int* __restrict__ flags, int ngrp)
@@ -100,15 +100,20 @@ __global__ __launch_bounds__(256, PT == 1 ? (NT <= 13 ? 4 : 3) : (NT <= 14 ? 3 :
     pow2_scale<13>(glb(P.mscale)[line], sM, invM);
     __shared__ HL Ms[2][MR * 256];
     f4 st[MR];
+    // column K has (NT - K) tiles of 64 quads: only the rounds of 256 quads that reach
+    // into it run (the condition is uniform, and fixed for each K of the unrolled loop)
     auto gload = [&](int K) __attribute__((always_inline)) {
         const int n = (NT - K) * 64;
         const f4* src = Ml + (size_t)tile_lc(K, K, NT) * 64;
 #pragma unroll
-        for (int i = 0; i < MR; ++i) st[i] = src[min(tid + 256 * i, n - 1)];
+        for (int i = 0; i < MR; ++i)
+            if (256 * i < n) st[i] = src[min(tid + 256 * i, n - 1)];
     };
-    auto lstore = [&](int buf) __attribute__((always_inline)) {
+    auto lstore = [&](int buf, int K) __attribute__((always_inline)) {
+        const int n = (NT - K) * 64;
 #pragma unroll
-        for (int i = 0; i < MR; ++i) Ms[buf][tid + 256 * i] = split16(st[i], sM);
+        for (int i = 0; i < MR; ++i)
+            if (256 * i < n) Ms[buf][tid + 256 * i] = split16(st[i], sM);
     };
     f4 y[2][PT];
     auto yload = [&](int K, f4* yy) __attribute__((always_inline)) {
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256, PT == 1 ? (NT <= 13 ? 4 : 3) : (NT <= 14 ? 3 :
     gload(0);
     yload(0, y[0]);
     mload(0, mv[0]);
-    lstore(0);
+    lstore(0, 0);
     __syncthreads();
 #pragma unroll
     for (int K = 0; K < NT; ++K) {
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(256, PT == 1 ? (NT <= 13 ? 4 : 3) : (NT <= 14 ? 3 :
             xm = xn;
         }
         __builtin_amdgcn_sched_barrier(0);
-        if (K + 1 < NT) lstore((K + 1) & 1);
+        if (K + 1 < NT) lstore((K + 1) & 1, K + 1);
         __syncthreads();
     }
     if (__ballot(ovf) && tid % 64 == 0) atomicOr(flags + line, FLAG_SCORE32);
