@@ -80,8 +80,11 @@ def summarize_trace(d, command, workload=WORKLOAD):
         if k is None:
             return name[:60] + ("..." if len(name) > 60 else "")
         if k in dup:
-            m = re.search(r"erx::(?:\(anonymous namespace\)::)?k_\w+?<([^>]*)>", name)
-            return f"{k}<{m.group(1).replace(' ', '')}>" if m else k
+            m = re.search(r"erx::(?:\(anonymous namespace\)::)?k_(\w+?)<([^>]*)>", name)
+            if not m:
+                return k
+            # the 128-band Gram kernel keeps its own name beside the 64-band one
+            return f"{'gram8' if m.group(1) == 'gram8' else k}<{m.group(2).replace(' ', '')}>"
         return k
 
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
