@@ -73,7 +73,7 @@ __device__ __forceinline__ HL split16(const f4 v, float s)
 // fewer accumulators per lane and more workgroups per line, two reuse each staged M tile
 // for twice the pixels)
 template <int NT, int DT, bool VEC, int PT>
-__global__ __launch_bounds__(256, PT == 1 ? (NT <= 14 ? 4 : 3) : (NT <= 14 ? 3 : 2)) void k_score16(const Pass P,
+__global__ __launch_bounds__(256, PT == 1 ? (NT <= 14 ? 4 : 3) : (NT <= 12 ? 3 : 2)) void k_score16(const Pass P,
                                                                                    const float* __restrict__ Mt,
                                                                     const float* __restrict__ mu32,
                                                                     int* __restrict__ flags, int ngrp)
