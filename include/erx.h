@@ -124,7 +124,10 @@ typedef struct erx_config {
     int gram_macro;    /* bands per macro tile (one workgroup's block of the Gram) of the split-FP16
                           Gram: 64 or 128; 0 (default): 128 from 65 bands on, else 64.  128-band
                           macro tiles split each element into its FP16 halves half as often at
-                          224 bands.  Results do not depend on it (both write the same values) */
+                          224 bands.  Results do not depend on it: both write the same values,
+                          except that a 128-band block the split cannot hold (a band constant
+                          over the first 64 pixels, or a value beyond the scale's headroom) is
+                          recomputed in FP32 as the four 64-band blocks it covers */
 } erx_config;
 
 enum { ERX_BG_EMA = 0, ERX_BG_IMC = 1 };

@@ -13,8 +13,9 @@
 // block (8x8 tiles of 16 bands) of the upper triangle of one line, so an
 // element is shifted, range-checked and split once per macro tile that needs
 // its band: at 224 bands twice (as a row and as a column), where 64-band macro
-// tiles do it four times.  That conversion, not the matrix cores, bounds the
-// split Gram.  Wave w owns tile row w mod 8 and tile columns 4 (w div 8) + 0..3
+// tiles do it four times; that conversion, not the matrix cores, bounded the
+// split Gram on 64-band macro tiles.  Here the per-chunk barrier makes the
+// staging and the products of all 16 waves take turns.  Wave w owns tile row w mod 8 and tile columns 4 (w div 8) + 0..3
 // of the macro tile (on a diagonal macro tile only those on or right of the
 // diagonal).
 //

@@ -71,7 +71,8 @@ __device__ __forceinline__ HL split16(const f4 v, float s)
 
 // PT: 16-pixel tiles per wave (the tile shape the autotuner chooses: one tile keeps
 // fewer accumulators per lane and more workgroups per line, two reuse each staged M tile
-// for twice the pixels)
+// for twice the pixels).  Waves per SIMD: as many as the registers allow without spills
+// (one tile: 124 VGPRs at 14 band tiles; two: 184 at 13-14)
 template <int NT, int DT, bool VEC, int PT>
 __global__ __launch_bounds__(256, PT == 1 ? (NT <= 14 ? 4 : 3) : (NT <= 12 ? 3 : 2)) void k_score16(const Pass P,
                                                                                    const float* __restrict__ Mt,
